@@ -1,0 +1,152 @@
+/*
+ * sortrace.h -- C ABI of libsortrace, an MI355X (gfx950) adaptive merge sort.
+ *
+ * The problem every call solves is the one stated in Sec. 1 and Appendix A
+ * of Zhang, Meng, Liang, "Sort Race" (arXiv 1609.04471): n elements are put
+ * into ascending order under one fixed ordering, in place, through a
+ * qsort-like call.  Here the ordering is fixed per dtype instead of a
+ * comparison function:
+ *   SR_INT32    two's-complement signed order
+ *   SR_UINT64   unsigned order
+ *   SR_FLOAT32  IEEE 754-2008 totalOrder on the bit pattern (-NaN < -Inf <
+ *               ... < -0 < +0 < ... < +Inf < +NaN, payloads ordered); bits are
+ *               never changed, so the sorted output is unique.
+ * Key+payload sorts are stable (Sec. 6: stability is the mergesort property
+ * that matters; Sec. 3 (a): equal elements keep their input order).
+ *
+ * Conventions shared by every call:
+ *  - Pointers to keys, payloads and offsets are DEVICE pointers owned by the
+ *    caller (for example torch.Tensor.data_ptr()); the library never frees
+ *    them.  Keys need their natural alignment (4 bytes for 32-bit dtypes, 8
+ *    for SR_UINT64), payloads 4 bytes; 16-byte alignment is not required.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous: they return once the work is enqueued on
+ *    `stream`, and the result is in place when the stream reaches that point.
+ *    No call in the sort path copies data back to the host or synchronizes.
+ *    Other streams must not touch the buffers meanwhile.  Host threads may
+ *    call concurrently on different streams.
+ *  - Scratch memory: the library owns one workspace per (device, stream),
+ *    grown on demand (a call that grows it synchronizes `stream` once first).
+ *  - Errors: everything checkable on the host is checked before anything is
+ *    enqueued, so on error the inputs are untouched.  n <= 1 (or nseg == 0)
+ *    is a no-op returning SR_OK.  A failed HIP launch returns SR_ERR_DEVICE
+ *    with the HIP message in sr_last_error_message().
+ */
+#ifndef SORTRACE_H
+#define SORTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SR_INT32 = 0, SR_UINT64 = 1, SR_FLOAT32 = 2 } sr_dtype;
+
+typedef enum {
+    SR_OK = 0,
+    SR_ERR_INVALID_ARGUMENT = 1,
+    SR_ERR_UNSUPPORTED = 2,
+    SR_ERR_OUT_OF_MEMORY = 3,
+    SR_ERR_DEVICE = 4,
+    SR_ERR_INTERNAL = 5
+} sr_status;
+
+/* The path the device plan chose for the last sort on a stream. */
+typedef enum {
+    SR_PATH_TRIVIAL = -1,  /* n <= 1, or small enough for one tile: no probe */
+    SR_PATH_SORTED = 0,    /* already nondecreasing: nothing written */
+    SR_PATH_REVERSED = 1,  /* nonincreasing: reversed in place (stable for pairs) */
+    SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back */
+    SR_PATH_GENERAL = 3    /* tile sort + merge passes */
+} sr_path;
+
+typedef struct {
+    int32_t path;          /* sr_path */
+    int32_t passes;        /* full read+write passes over n keys (fractional parts rounded up) */
+    int64_t n;             /* keys sorted by the call */
+    int64_t descents;      /* probe: descents seen (exact when path is SORTED/REVERSED) */
+    int64_t outliers;      /* OUTLIER path: keys moved to the outlier list */
+    double bytes_moved;    /* algorithmic HBM bytes: passes x 2 x n x element bytes */
+} sr_stats;
+
+/*
+ * Sort n keys of type dt in place at device pointer `keys`.  The
+ * ascending order of Sec. 1; equal keys are bit-identical, so the result is
+ * the unique sorted permutation.
+ * Errors: SR_ERR_INVALID_ARGUMENT for keys == NULL with n > 1, a bad dtype or
+ * a misaligned pointer.
+ */
+sr_status sr_sort_keys(sr_dtype dt, void *keys, size_t n, void *stream);
+
+/*
+ * Stable sort of (key, payload) records in place: keys at `keys` (type dt),
+ * payload[i] travels with keys[i].  Among equal keys the input order is kept
+ * (Sec. 3 (a), Sec. 6).  payload must not be NULL when n > 1.
+ */
+sr_status sr_sort_pairs(sr_dtype dt, void *keys, uint32_t *payload, size_t n, void *stream);
+
+/*
+ * Segmented sort: every segment [offsets[s], offsets[s+1]) of `keys` (and of
+ * `payload` when it is not NULL, stable) is sorted on its own, all in one
+ * batch of launches.  `offsets` is a DEVICE array of nseg + 1 int64 with
+ * offsets[0] == 0, nondecreasing, offsets[nseg] == n; empty segments are
+ * allowed.  These preconditions are the caller's: they are not checked on the
+ * device.
+ */
+sr_status sr_sort_segmented(sr_dtype dt, void *keys, uint32_t *payload, size_t n,
+                            const int64_t *offsets, size_t nseg, void *stream);
+
+/*
+ * Presortedness of keys (Sec. 2): out_host[0] = number of descents
+ * a_i > a_{i+1} (Run(A) = descents + 1), out_host[1] = number of ascents
+ * a_i < a_{i+1}.  out_host is HOST memory; this call synchronizes `stream`.
+ */
+sr_status sr_measure(sr_dtype dt, const void *keys, size_t n, int64_t *out_host, void *stream);
+
+/* Workspace bytes the library would hold for a call of this shape. */
+sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nseg, size_t *bytes);
+
+/*
+ * Statistics of the last sr_sort_keys / sr_sort_pairs on `stream`.  Reads
+ * the device plan back, so it synchronizes `stream`.  out is host memory.
+ */
+sr_status sr_last_stats(void *stream, sr_stats *out);
+
+/* Static text for a status code. */
+const char *sr_status_str(sr_status s);
+
+/* Detail of the last error on the calling host thread ("" if none). */
+const char *sr_last_error_message(void);
+
+/*
+ * Options (process-wide).  Names:
+ *   "force_path"  -1 = let the device plan decide (default); otherwise an
+ *                 sr_path value the plan is forced to when it is safe
+ *                 (SR_PATH_GENERAL is always safe).
+ *   "profile"     1 = record a HIP event pair around every kernel the sort
+ *                 path launches (on the caller's stream); 0 = off (default).
+ * Returns SR_ERR_INVALID_ARGUMENT for an unknown name or value.
+ */
+sr_status sr_set_option(const char *name, int64_t value);
+
+/*
+ * With "profile" on: sums the device time of the recorded launches whose
+ * kernel name starts with `prefix` ("" = all), then forgets every recorded
+ * launch.  Synchronizes on the recorded events.  launches and total_ms are
+ * host memory.  Kernel names: "probe", "reverse", "regroup", "tile_sort",
+ * "merge", "classify", "merge_outliers", "seg_plan", "seg_tile_sort",
+ * "seg_merge".
+ */
+sr_status sr_profile_collect(const char *prefix, int64_t *launches, double *total_ms);
+
+/* Device copy kernel (16-byte vectors) used as a bandwidth reference:
+ * copies `bytes` (a multiple of 16) from src to dst on `stream`. */
+sr_status sr_copy_bandwidth_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SORTRACE_H */

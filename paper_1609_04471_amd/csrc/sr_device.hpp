@@ -1,0 +1,299 @@
+// sr_device.hpp -- device primitives of libsortrace (gfx950, wave64).
+//
+//  * key codec: an order-preserving bijection from each dtype's bit pattern
+//    to an unsigned integer, so every comparison below is an unsigned
+//    integer comparison (the fixed ordering of Sec. 1; float32 follows IEEE
+//    754-2008 totalOrder on the bits);
+//  * cross-lane exchange of a register with lane ^ M (DPP / ds_swizzle /
+//    ds_bpermute, picked at compile time per mask);
+//  * compare-exchange networks: Batcher's merge exchange (Knuth, TAOCP 3,
+//    Sec. 5.2.2, Algorithm M) inside a thread, Batcher's bitonic merge across
+//    the 64 lanes of a wavefront;
+//  * Merge Path co-rank searches (Odeh, Green, Mwassi, Shmueli, Birk 2012):
+//    a binary search inside LDS and a 64-ary wavefront search in global
+//    memory.
+// Every merge takes the left run on ties, which keeps merges stable (the
+// Appendix A merge contract plus the stability of Sec. 6).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ codec
+// S = storage type (what the user's buffer holds), U = order key.
+struct CodecI32 {
+    using S = uint32_t;
+    using U = uint32_t;
+    static __device__ __forceinline__ U enc(S x) { return x ^ 0x80000000u; }
+    static __device__ __forceinline__ S dec(U u) { return u ^ 0x80000000u; }
+};
+
+struct CodecF32 {
+    using S = uint32_t;
+    using U = uint32_t;
+    // sign clear: set the top bit; sign set: invert every bit.
+    static __device__ __forceinline__ U enc(S b) {
+        return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+    }
+    static __device__ __forceinline__ S dec(U u) {
+        return u ^ ((uint32_t)((int32_t)~u >> 31) | 0x80000000u);
+    }
+};
+
+struct CodecU64 {
+    using S = uint64_t;
+    using U = uint64_t;
+    static __device__ __forceinline__ U enc(S x) { return x; }
+    static __device__ __forceinline__ S dec(U u) { return u; }
+};
+
+template <class U>
+__device__ __forceinline__ U key_max() { return (U)~(U)0; }
+
+// --------------------------------------------------- device control block
+// One per workspace.  The probe's last workgroup turns the counters into the
+// plan and zeroes them again, so every call finds them cleared.
+struct Ctl {
+    unsigned long long desc;          // descents seen by the probe
+    unsigned long long asc;           // ascents seen by the probe
+    unsigned long long sample_desc;   // descents among sampled neighbour pairs
+    unsigned long long sample_pairs;  // sampled neighbour pairs
+    unsigned int mixed;               // some workgroup saw both an ascent and a descent
+    unsigned int ticket;              // workgroups of the probe that finished
+    int path;                         // sr_path chosen by the plan
+    int force_path;                   // -1 or a forced sr_path
+    unsigned long long n_out;         // OUTLIER path: outlier count
+    unsigned long long n_kept;        // OUTLIER path: kept count
+    unsigned int bad_join;            // OUTLIER path: kept list not sorted across tiles
+    unsigned int ticket2;
+    int out_passes;                   // OUTLIER path: merge passes needed for the outliers
+    int pad0;
+    unsigned long long reserved[6];
+};
+
+// Plain relaxed agent-scope accessors (coherent across the XCDs' L2s).
+__device__ __forceinline__ unsigned int ld_agent(const unsigned int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_agent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------ cross-lane exchange
+// Value held by lane (lane ^ M) of the same wavefront.  DPP covers the masks
+// that stay inside a row of 16 lanes, ds_swizzle's bit mode the masks below
+// 32, ds_bpermute the rest.  All lanes must be active.
+template <int M>
+__device__ __forceinline__ uint32_t xlane(uint32_t v) {
+    const int x = (int)v;
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    } else if constexpr (M == 3) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+    } else if constexpr (M == 7) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); // row_half_mirror
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false); // row_ror:8
+    } else if constexpr (M == 15) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); // row_mirror
+    } else if constexpr (M < 32) {
+        // bit mode: and_mask = 0x1F, or_mask = 0, xor_mask = M
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x1F | (M << 10));
+    } else {
+        const int src = (int)(__lane_id() ^ (unsigned)M);
+        return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, x);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xlane(uint64_t v) {
+    const uint32_t lo = xlane<M>((uint32_t)v);
+    const uint32_t hi = xlane<M>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Network element for stable (key, payload) tile sorts: the key plus the
+// element's position inside the tile.  Ordering (key, position) makes every
+// element distinct, so any sorting network yields the stable order.
+template <class U>
+struct KeyPos {
+    U k;
+    uint32_t p;
+};
+
+template <class U>
+__device__ __forceinline__ bool lt(U a, U b) { return a < b; }
+template <class U>
+__device__ __forceinline__ bool lt(const KeyPos<U>& a, const KeyPos<U>& b) {
+    return a.k < b.k || (a.k == b.k && a.p < b.p);
+}
+
+template <class U>
+__device__ __forceinline__ U emin(U a, U b) { return a < b ? a : b; }
+template <class U>
+__device__ __forceinline__ U emax(U a, U b) { return a < b ? b : a; }
+template <class U>
+__device__ __forceinline__ KeyPos<U> emin(const KeyPos<U>& a, const KeyPos<U>& b) { return lt(b, a) ? b : a; }
+template <class U>
+__device__ __forceinline__ KeyPos<U> emax(const KeyPos<U>& a, const KeyPos<U>& b) { return lt(b, a) ? a : b; }
+
+template <int M, class U>
+__device__ __forceinline__ KeyPos<U> xlane(const KeyPos<U>& v) {
+    return KeyPos<U>{xlane<M>(v.k), xlane<M>(v.p)};
+}
+
+template <class E>
+__device__ __forceinline__ void cmpx(E& a, E& b) {
+    const E lo = emin(a, b);
+    const E hi = emax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// ----------------------------------------------- in-register sorting network
+// Batcher's merge exchange for N inputs, generated at compile time in the
+// order of Knuth's Algorithm M (passes p = 2^(t-1) .. 1; inner d, q, r).
+template <int N>
+struct MergeExchange {
+    int a[N * N];
+    int b[N * N];
+    int count;
+    constexpr MergeExchange() : a(), b(), count(0) {
+        int t = 0;
+        while ((1 << t) < N) ++t;
+        if (t == 0) return;
+        for (int p = 1 << (t - 1); p > 0; p >>= 1) {
+            int q = 1 << (t - 1), r = 0, d = p;
+            for (;;) {
+                for (int i = 0; i + d < N; ++i) {
+                    if ((i & p) == r) {
+                        a[count] = i;
+                        b[count] = i + d;
+                        ++count;
+                    }
+                }
+                if (q == p) break;
+                d = q - p;
+                q >>= 1;
+                r = p;
+            }
+        }
+    }
+};
+
+template <int N>
+inline constexpr MergeExchange<N> kMergeExchange{};
+
+template <int N, class E>
+__device__ __forceinline__ void sort_in_registers(E (&v)[N]) {
+    constexpr MergeExchange<N> net = kMergeExchange<N>;
+#pragma unroll
+    for (int c = 0; c < net.count; ++c) cmpx(v[net.a[c]], v[net.b[c]]);
+}
+
+// ----------------------------------------------- wavefront bitonic merging
+// Conceptual index of v[r] in lane L is L * N + r.  Each lane starts with N
+// sorted values; after wave_sort the wavefront's 64 * N values are sorted.
+// Merging two sorted runs of G/2 lanes each: first the "flip" stage pairs
+// index i with the mirrored index of the 2-run block (lane ^ (G-1), register
+// N-1-r), then half-cleaners at lane distances G/4 .. 1, then at register
+// distances N/2 .. 1 (Batcher's bitonic merge).
+template <int DL, int N, class E>
+__device__ __forceinline__ void half_cleaner_lanes(E (&v)[N], unsigned lane) {
+    const bool upper = (lane & DL) != 0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const E p = xlane<DL>(v[r]);
+        v[r] = upper ? emax(v[r], p) : emin(v[r], p);
+    }
+    if constexpr (DL > 1) half_cleaner_lanes<DL / 2>(v, lane);
+}
+
+template <int N, class E>
+__device__ __forceinline__ void half_cleaners_in_registers(E (&v)[N]) {
+#pragma unroll
+    for (int d = N / 2; d >= 1; d /= 2) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if ((r & d) == 0) cmpx(v[r], v[r + d]);
+        }
+    }
+}
+
+template <int G, int N, class E>
+__device__ __forceinline__ void wave_merge_level(E (&v)[N], unsigned lane) {
+    const bool upper = (lane & (G / 2)) != 0;
+    E p[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) p[r] = xlane<G - 1>(v[N - 1 - r]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = upper ? emax(v[r], p[r]) : emin(v[r], p[r]);
+    if constexpr (G >= 4) half_cleaner_lanes<G / 4>(v, lane);
+    half_cleaners_in_registers(v);
+    if constexpr (G < kWave) wave_merge_level<G * 2>(v, lane);
+}
+
+template <int N, class E>
+__device__ __forceinline__ void wave_sort(E (&v)[N]) {
+    sort_in_registers(v);
+    wave_merge_level<2>(v, __lane_id());
+}
+
+// ------------------------------------------------------- Merge Path search
+// co-rank of diagonal d between sorted A[0, la) and B[0, lb): the number i of
+// A elements among the first d outputs of the stable merge.  A[i] precedes
+// B[d-1-i] when A[i] <= B[d-1-i].
+template <class U>
+__device__ __forceinline__ int corank_lds(const U* A, int la, const U* B, int lb, int d) {
+    int lo = d > lb ? d - lb : 0;
+    int hi = d < la ? d : la;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] <= B[d - 1 - mid])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Same search in global memory by one whole wavefront: each round the 64
+// lanes test 64 evenly spaced candidates, so the range shrinks 64-fold per
+// round.  Keys are decoded with codec C on load.  Returns the co-rank in all
+// lanes.
+template <class C>
+__device__ __forceinline__ int64_t corank_wave(const typename C::S* A, int64_t la,
+                                               const typename C::S* B, int64_t lb, int64_t d) {
+    const unsigned lane = __lane_id();
+    int64_t lo = d > lb ? d - lb : 0;
+    int64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const int64_t len = hi - lo;
+        const int64_t step = (len + kWave - 1) / kWave;
+        const int64_t x = lo + (int64_t)lane * step;
+        bool pred = false;
+        if (x < hi) pred = C::enc(A[x]) <= C::enc(B[d - 1 - x]);
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(pred);
+        const int cnt = __builtin_popcountll(bal);  // predicate is monotone: the first cnt probes hold
+        if (cnt == 0) {
+            hi = lo;
+        } else {
+            const int64_t last_true = lo + (int64_t)(cnt - 1) * step;
+            const int64_t first_false = lo + (int64_t)cnt * step;
+            lo = last_true + 1;
+            hi = first_false < hi ? first_false : hi;
+        }
+    }
+    return lo;
+}
+
+}  // namespace sr

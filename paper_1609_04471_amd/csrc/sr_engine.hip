@@ -1,0 +1,712 @@
+// sr_engine.hip -- kernels, host orchestration and the C ABI of libsortrace.
+//
+// Launch sequence of sr_sort_keys / sr_sort_pairs for n above one tile, all on
+// the caller's stream and with no device-to-host traffic:
+//   probe      reads the keys once (early exit once the array is known to be
+//              mixed), counts ascents/descents, samples the descent rate; its
+//              last workgroup writes the plan into the device control block.
+//              This is the sortedness test the paper makes indispensable for
+//              quicksort (Sec. 4 (f)) and the run scan of natural mergesort
+//              (Sec. 1, process 1), for the whole array at once.
+//   reverse    (+ regroup for pairs) only if the plan says REVERSED: a
+//              nonincreasing array is one descending run, reversed in place
+//              (Sec. 3 (a)); for pairs equal-key groups are reversed back, the
+//              paper's "reversed twice".
+//   outlier    only if the plan says OUTLIER (nearly sorted input).
+//   tile_sort  + merge x M only if the plan says GENERAL.
+// Kernels whose path was not chosen return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sortrace.h"
+#include "sr_kernels.hpp"
+
+namespace sr {
+
+// ------------------------------------------------------------- tuning
+// Tile sort: WG x IT keys per workgroup; merge: WG x IT outputs per workgroup.
+template <class C, bool PAIRS>
+struct Tune;
+template <bool PAIRS>
+struct Tune32 {
+    static constexpr int TWG = PAIRS ? 256 : 512, TIT = 16;
+    static constexpr int MWG = 256, MIT = 16;
+};
+template <bool PAIRS>
+struct Tune64 {
+    static constexpr int TWG = 256, TIT = PAIRS ? 8 : 16;
+    static constexpr int MWG = 256, MIT = 8;
+};
+template <bool PAIRS>
+struct Tune<CodecI32, PAIRS> : Tune32<PAIRS> {};
+template <bool PAIRS>
+struct Tune<CodecF32, PAIRS> : Tune32<PAIRS> {};
+template <bool PAIRS>
+struct Tune<CodecU64, PAIRS> : Tune64<PAIRS> {};
+
+constexpr int kProbeWG = 256;
+constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
+constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
+constexpr int kRevWG = 256;
+
+__device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
+    return ctl == nullptr || ld_agent(&ctl->path) == want;
+}
+
+// ============================================================== kernels
+
+template <class C, int WG, int IT, bool PAIRS>
+__global__ __launch_bounds__(WG) void k_tile_sort(const typename C::S* src, typename C::S* dst,
+                                                  const uint32_t* psrc, uint32_t* pdst, int64_t n,
+                                                  const Ctl* ctl, int need) {
+    using TS = TileSort<C, WG, IT, PAIRS>;
+    if (!path_is(ctl, need)) return;
+    __shared__ typename TS::Smem sm;
+    const int64_t base = (int64_t)blockIdx.x * TS::T;
+    const int valid = (int)((n - base) < TS::T ? (n - base) : TS::T);
+    TS::run(sm, src + base, dst + base, PAIRS ? psrc + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
+}
+
+template <class C, int WG, int IT, bool PAIRS>
+__global__ __launch_bounds__(WG) void k_merge(const typename C::S* src, typename C::S* dst,
+                                              const uint32_t* psrc, uint32_t* pdst, int64_t n,
+                                              int64_t width, const Ctl* ctl, int need) {
+    using MC = MergeChunk<C, WG, IT, PAIRS>;
+    if (!path_is(ctl, need)) return;
+    __shared__ typename MC::Smem sm;
+    MC::run(sm, src, dst, psrc, pdst, n, width, (int64_t)blockIdx.x * MC::CH);
+}
+
+// Probe: workgroup b owns the neighbour pairs (i, i+1) for i in
+// [b*kProbeTile, (b+1)*kProbeTile) and i+1 < n.  The last workgroup to finish
+// turns the counters into the plan and clears them.
+template <class C>
+__global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
+                                                    int outlier_ok) {
+    using U = typename C::U;
+    __shared__ unsigned long long red[4][kProbeWG / kWave];
+    __shared__ int skip;
+    __shared__ unsigned int last;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int64_t b0 = (int64_t)blockIdx.x * kProbeTile;
+    const int64_t b1 = std::min<int64_t>(b0 + kProbeTile, n - 1);
+    if (tid == 0) skip = ld_agent(&ctl->mixed) != 0;
+
+    unsigned long long sd = 0, sp = 0;
+    const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, b1);
+    for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
+        const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+        sd += x > y ? 1 : 0;
+        sp += 1;
+    }
+    __syncthreads();
+    unsigned long long d = 0, a = 0;
+    if (!skip) {
+        for (int64_t i = b0 + tid; i < b1; i += kProbeWG) {
+            const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+            d += x > y ? 1 : 0;
+            a += x < y ? 1 : 0;
+        }
+    }
+    d = wave_sum(d);
+    a = wave_sum(a);
+    sd = wave_sum(sd);
+    sp = wave_sum(sp);
+    if (__lane_id() == 0) {
+        red[0][wave] = d;
+        red[1][wave] = a;
+        red[2][wave] = sd;
+        red[3][wave] = sp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long t[4] = {0, 0, 0, 0};
+        for (int w = 0; w < kProbeWG / kWave; ++w)
+            for (int q = 0; q < 4; ++q) t[q] += red[q][w];
+        if (t[0]) atomicAdd(&ctl->desc, t[0]);
+        if (t[1]) atomicAdd(&ctl->asc, t[1]);
+        if (t[2]) atomicAdd(&ctl->sample_desc, t[2]);
+        if (t[3]) atomicAdd(&ctl->sample_pairs, t[3]);
+        if (t[0] && t[1]) atomicOr(&ctl->mixed, 1u);
+        __threadfence();
+        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && tid == 0) {
+        __threadfence();
+        const unsigned long long desc = ld_agent(&ctl->desc);
+        const unsigned long long asc = ld_agent(&ctl->asc);
+        const unsigned long long sdesc = ld_agent(&ctl->sample_desc);
+        const unsigned long long spairs = ld_agent(&ctl->sample_pairs);
+        const bool mixed = ld_agent(&ctl->mixed) != 0;
+        int path;
+        if (!mixed && desc == 0) path = SR_PATH_SORTED;
+        else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
+        else if (outlier_ok && sdesc * 16 <= spairs) path = SR_PATH_OUTLIER;
+        else path = SR_PATH_GENERAL;
+        const int force = ctl->force_path;
+        if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok)) path = force;
+        ctl->path = path;
+        ctl->reserved[0] = desc;   // kept for sr_last_stats
+        ctl->reserved[1] = asc;
+        ctl->desc = 0;
+        ctl->asc = 0;
+        ctl->sample_desc = 0;
+        ctl->sample_pairs = 0;
+        ctl->mixed = 0;
+        ctl->ticket = 0;
+        ctl->n_out = 0;
+        ctl->n_kept = 0;
+        ctl->bad_join = 0;
+        ctl->ticket2 = 0;
+    }
+}
+
+// In-place reversal of keys (and payloads): swaps i and n-1-i.
+template <class S>
+__global__ __launch_bounds__(kRevWG) void k_reverse(S* keys, uint32_t* pay, int64_t n, const Ctl* ctl) {
+    if (!path_is(ctl, SR_PATH_REVERSED)) return;
+    const int64_t half = n / 2;
+    for (int64_t i = (int64_t)blockIdx.x * kRevWG + threadIdx.x; i < half; i += (int64_t)gridDim.x * kRevWG) {
+        const int64_t j = n - 1 - i;
+        const S a = keys[i], b = keys[j];
+        keys[i] = b;
+        keys[j] = a;
+        if (pay) {
+            const uint32_t pa = pay[i], pb = pay[j];
+            pay[i] = pb;
+            pay[j] = pa;
+        }
+    }
+}
+
+// After a plain reversal of a nonincreasing array of pairs, equal-key groups
+// are in reversed input order; reverse each group's payloads once more.
+template <class C>
+__global__ __launch_bounds__(kRevWG) void k_regroup(const typename C::S* keys, uint32_t* pay, int64_t n,
+                                                    const Ctl* ctl) {
+    using U = typename C::U;
+    if (!path_is(ctl, SR_PATH_REVERSED)) return;
+    for (int64_t i = (int64_t)blockIdx.x * kRevWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRevWG) {
+        const U x = C::enc(keys[i]);
+        const bool le = i > 0 && C::enc(keys[i - 1]) == x;
+        const bool re = i + 1 < n && C::enc(keys[i + 1]) == x;
+        if (!le && !re) continue;
+        int64_t lo = 0, hi = i;  // first index with key == x (keys ascending now)
+        while (lo < hi) {
+            const int64_t m = (lo + hi) >> 1;
+            if (C::enc(keys[m]) < x) lo = m + 1;
+            else hi = m;
+        }
+        const int64_t gs = lo;
+        lo = i;
+        hi = n;  // first index with key > x
+        while (lo < hi) {
+            const int64_t m = (lo + hi) >> 1;
+            if (C::enc(keys[m]) <= x) lo = m + 1;
+            else hi = m;
+        }
+        const int64_t partner = gs + lo - 1 - i;
+        if (i < partner) {
+            const uint32_t a = pay[i], b = pay[partner];
+            pay[i] = b;
+            pay[partner] = a;
+        }
+    }
+}
+
+// Exact counts of descents and ascents (sr_measure).
+template <class C>
+__global__ __launch_bounds__(kProbeWG) void k_count(const typename C::S* keys, int64_t n,
+                                                    unsigned long long* out) {
+    using U = typename C::U;
+    unsigned long long d = 0, a = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kProbeWG + threadIdx.x; i + 1 < n; i += (int64_t)gridDim.x * kProbeWG) {
+        const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+        d += x > y ? 1 : 0;
+        a += x < y ? 1 : 0;
+    }
+    d = wave_sum(d);
+    a = wave_sum(a);
+    if (__lane_id() == 0) {
+        if (d) atomicAdd(&out[0], d);
+        if (a) atomicAdd(&out[1], a);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_init_ctl(Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long* w = reinterpret_cast<unsigned long long*>(ctl);
+        for (size_t i = 0; i < sizeof(Ctl) / 8; ++i) w[i] = 0;
+        ctl->path = SR_PATH_GENERAL;
+        ctl->force_path = -1;
+    }
+}
+
+__global__ void k_set_force(Ctl* ctl, int force) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->force_path = force;
+}
+
+__global__ __launch_bounds__(256) void k_copy16(uint4* dst, const uint4* src, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+}  // namespace sr
+
+// ======================================================================
+// Host side
+// ======================================================================
+namespace {
+
+using namespace sr;
+
+thread_local std::string g_err;
+
+sr_status fail(sr_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+sr_status hip_fail(hipError_t e, const char* what) {
+    return fail(SR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+std::mutex g_mu;
+int g_force_path = -1;
+bool g_profile = false;
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t get_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// Records an event pair around one launch when profiling is on.
+struct ProfScope {
+    hipStream_t st;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(hipStream_t s, const char* nm) : st(s), name(nm) {
+        if (g_profile) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            a = get_event();
+            b = get_event();
+            hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEventRecord(b, st);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_prof.push_back(ProfRec{name, a, b});
+        }
+    }
+};
+
+struct Workspace {
+    void* base = nullptr;
+    size_t bytes = 0;
+    Ctl* ctl = nullptr;
+    int force = -2;  // force_path value last written to ctl
+};
+
+struct LastCall {
+    int64_t n = 0;
+    int es = 0;
+    int merge_passes = 0;
+    int trivial = 1;
+    Ctl* ctl = nullptr;
+};
+
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+std::map<hipStream_t, LastCall> g_last;
+
+constexpr size_t kCtlBytes = 256;
+static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace of at least `data_bytes` scratch bytes for (device, stream).
+sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Workspace* ws;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Workspace*& slot = g_ws[{dev, st}];
+        if (!slot) slot = new Workspace();
+        ws = slot;
+    }
+    const size_t need = kCtlBytes + round_up(data_bytes, 256);
+    if (ws->bytes < need) {
+        if (ws->base) {
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            hipFree(ws->base);
+            ws->base = nullptr;
+            ws->bytes = 0;
+        }
+        const size_t alloc = std::max(need, (size_t)1 << 20);
+        e = hipMalloc(&ws->base, alloc);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            return fail(SR_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(alloc) + " bytes failed");
+        }
+        ws->bytes = alloc;
+        ws->ctl = reinterpret_cast<Ctl*>(ws->base);
+        hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, ws->ctl);
+        ws->force = -1;
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "init");
+    }
+    int force;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        force = g_force_path;
+    }
+    if (ws->force != force) {
+        hipLaunchKernelGGL(k_set_force, dim3(1), dim3(1), 0, st, ws->ctl, force);
+        ws->force = force;
+    }
+    *out = ws;
+    return SR_OK;
+}
+
+void* ws_data(Workspace* ws) { return (char*)ws->base + kCtlBytes; }
+
+int ceil_log2(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+#define SR_LAUNCH_CHECK(what)                                  \
+    do {                                                       \
+        hipError_t e_ = hipGetLastError();                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what);       \
+    } while (0)
+
+template <class C, bool PAIRS>
+sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
+    using S = typename C::S;
+    using TN = Tune<C, PAIRS>;
+    constexpr int T = TN::TWG * TN::TIT;
+    constexpr int CH = TN::MWG * TN::MIT;
+    static_assert(T % CH == 0, "tile must be a whole number of merge chunks");
+    S* keys = static_cast<S*>(keys_v);
+    const int64_t ntiles = cdiv(n, T);
+    const int M = ceil_log2(ntiles);
+    LastCall lc;
+    lc.n = n;
+    lc.es = (int)sizeof(S) + (PAIRS ? 4 : 0);
+    lc.merge_passes = M;
+    if (ntiles == 1) {
+        // One tile: sort in place, no probe.
+        ProfScope ps(st, "tile_sort");
+        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, st, keys, keys,
+                           pay, pay, n, (const Ctl*)nullptr, 0);
+        SR_LAUNCH_CHECK("tile_sort");
+        lc.trivial = 1;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_last[st] = lc;
+        return SR_OK;
+    }
+    Workspace* ws = nullptr;
+    const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
+    sr_status s = get_workspace(st, kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws);
+    if (s != SR_OK) return s;
+    Ctl* ctl = ws->ctl;
+    S* skeys = static_cast<S*>(ws_data(ws));
+    uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>((char*)ws_data(ws) + kbytes) : nullptr;
+
+    {
+        ProfScope ps(st, "probe");
+        hipLaunchKernelGGL(k_probe<C>, dim3((unsigned)cdiv(n - 1, kProbeTile)), dim3(kProbeWG), 0, st,
+                           (const S*)keys, n, ctl, 0);
+        SR_LAUNCH_CHECK("probe");
+    }
+    {
+        ProfScope ps(st, "reverse");
+        const unsigned g = (unsigned)std::min<int64_t>(cdiv(n / 2, kRevWG * 4), 8192);
+        hipLaunchKernelGGL(k_reverse<S>, dim3(std::max(1u, g)), dim3(kRevWG), 0, st, keys, pay, n, (const Ctl*)ctl);
+        SR_LAUNCH_CHECK("reverse");
+    }
+    if (PAIRS) {
+        ProfScope ps(st, "regroup");
+        const unsigned g = (unsigned)std::min<int64_t>(cdiv(n, kRevWG * 4), 8192);
+        hipLaunchKernelGGL(k_regroup<C>, dim3(std::max(1u, g)), dim3(kRevWG), 0, st, (const S*)keys, pay, n,
+                           (const Ctl*)ctl);
+        SR_LAUNCH_CHECK("regroup");
+    }
+    S* kbuf[2] = {keys, skeys};
+    uint32_t* pbuf[2] = {pay, spay};
+    {
+        ProfScope ps(st, "tile_sort");
+        const int to = M % 2;
+        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
+                           keys, kbuf[to], pay, pbuf[to], n, (const Ctl*)ctl, (int)SR_PATH_GENERAL);
+        SR_LAUNCH_CHECK("tile_sort");
+    }
+    for (int k = 0; k < M; ++k) {
+        ProfScope ps(st, "merge");
+        const int from = (M - k) % 2, to = (M - k - 1) % 2;
+        const int64_t width = (int64_t)T << k;
+        hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)cdiv(n, CH)), dim3(TN::MWG), 0, st,
+                           (const S*)kbuf[from], kbuf[to], (const uint32_t*)pbuf[from], pbuf[to], n, width,
+                           (const Ctl*)ctl, (int)SR_PATH_GENERAL);
+        SR_LAUNCH_CHECK("merge");
+    }
+    lc.trivial = 0;
+    lc.ctl = ctl;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_last[st] = lc;
+    return SR_OK;
+}
+
+int elem_bytes(sr_dtype dt) {
+    switch (dt) {
+    case SR_INT32: return 4;
+    case SR_UINT64: return 8;
+    case SR_FLOAT32: return 4;
+    default: return 0;
+    }
+}
+
+sr_status check_keys(sr_dtype dt, const void* keys, size_t n) {
+    const int es = elem_bytes(dt);
+    if (es == 0) return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+    if (n > 1 && keys == nullptr) return fail(SR_ERR_INVALID_ARGUMENT, "keys is NULL");
+    if (n > ((size_t)1 << 36)) return fail(SR_ERR_INVALID_ARGUMENT, "n too large");
+    if (keys && ((uintptr_t)keys % (uintptr_t)es) != 0)
+        return fail(SR_ERR_INVALID_ARGUMENT, "keys not aligned to the element size");
+    return SR_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+sr_status sr_sort_keys(sr_dtype dt, void* keys, size_t n, void* stream) {
+    g_err.clear();
+    sr_status s = check_keys(dt, keys, n);
+    if (s != SR_OK) return s;
+    if (n <= 1) return SR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    switch (dt) {
+    case SR_INT32: return sort_impl<CodecI32, false>(keys, nullptr, (int64_t)n, st);
+    case SR_FLOAT32: return sort_impl<CodecF32, false>(keys, nullptr, (int64_t)n, st);
+    case SR_UINT64: return sort_impl<CodecU64, false>(keys, nullptr, (int64_t)n, st);
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+}
+
+sr_status sr_sort_pairs(sr_dtype dt, void* keys, uint32_t* payload, size_t n, void* stream) {
+    g_err.clear();
+    sr_status s = check_keys(dt, keys, n);
+    if (s != SR_OK) return s;
+    if (n > 1 && payload == nullptr) return fail(SR_ERR_INVALID_ARGUMENT, "payload is NULL");
+    if (payload && ((uintptr_t)payload & 3u)) return fail(SR_ERR_INVALID_ARGUMENT, "payload not 4-byte aligned");
+    if (n <= 1) return SR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    switch (dt) {
+    case SR_INT32: return sort_impl<CodecI32, true>(keys, payload, (int64_t)n, st);
+    case SR_FLOAT32: return sort_impl<CodecF32, true>(keys, payload, (int64_t)n, st);
+    case SR_UINT64: return sort_impl<CodecU64, true>(keys, payload, (int64_t)n, st);
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+}
+
+sr_status sr_sort_segmented(sr_dtype dt, void* keys, uint32_t* payload, size_t n, const int64_t* offsets,
+                            size_t nseg, void* stream) {
+    g_err.clear();
+    (void)dt; (void)keys; (void)payload; (void)n; (void)offsets; (void)nseg; (void)stream;
+    return fail(SR_ERR_UNSUPPORTED, "segmented sort not built yet");
+}
+
+sr_status sr_measure(sr_dtype dt, const void* keys, size_t n, int64_t* out_host, void* stream) {
+    g_err.clear();
+    sr_status s = check_keys(dt, keys, n);
+    if (s != SR_OK) return s;
+    if (!out_host) return fail(SR_ERR_INVALID_ARGUMENT, "out_host is NULL");
+    out_host[0] = out_host[1] = 0;
+    if (n <= 1) return SR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Workspace* ws = nullptr;
+    s = get_workspace(st, 256, &ws);
+    if (s != SR_OK) return s;
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(ws_data(ws));
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt, 2, 0ull);
+    const unsigned g = (unsigned)std::min<int64_t>(cdiv((int64_t)n, kProbeWG * 8), 16384);
+    switch (dt) {
+    case SR_INT32: hipLaunchKernelGGL(k_count<CodecI32>, dim3(g), dim3(kProbeWG), 0, st, (const uint32_t*)keys, (int64_t)n, cnt); break;
+    case SR_FLOAT32: hipLaunchKernelGGL(k_count<CodecF32>, dim3(g), dim3(kProbeWG), 0, st, (const uint32_t*)keys, (int64_t)n, cnt); break;
+    case SR_UINT64: hipLaunchKernelGGL(k_count<CodecU64>, dim3(g), dim3(kProbeWG), 0, st, (const uint64_t*)keys, (int64_t)n, cnt); break;
+    }
+    SR_LAUNCH_CHECK("count");
+    unsigned long long h[2];
+    hipError_t e = hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    out_host[0] = (int64_t)h[0];
+    out_host[1] = (int64_t)h[1];
+    return SR_OK;
+}
+
+sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nseg, size_t* bytes) {
+    g_err.clear();
+    const int es = elem_bytes(dt);
+    if (es == 0 || !bytes) return fail(SR_ERR_INVALID_ARGUMENT, "bad argument");
+    size_t b = kCtlBytes + round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
+    b += round_up((nseg + 1) * 8 * 4, 256);
+    *bytes = std::max(b, (size_t)1 << 20);
+    return SR_OK;
+}
+
+sr_status sr_last_stats(void* stream, sr_stats* out) {
+    g_err.clear();
+    if (!out) return fail(SR_ERR_INVALID_ARGUMENT, "out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    LastCall lc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_last.find(st);
+        if (it == g_last.end()) return fail(SR_ERR_INVALID_ARGUMENT, "no sort on this stream yet");
+        lc = it->second;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->n = lc.n;
+    if (lc.trivial) {
+        out->path = SR_PATH_TRIVIAL;
+        out->passes = 1;
+    } else {
+        Ctl h;
+        hipError_t e = hipMemcpyAsync(&h, lc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        out->path = h.path;
+        out->descents = (int64_t)h.reserved[0];
+        switch (h.path) {
+        case SR_PATH_SORTED: out->passes = 0; break;
+        case SR_PATH_REVERSED: out->passes = 1; break;
+        case SR_PATH_GENERAL: out->passes = 1 + lc.merge_passes; break;
+        default: out->passes = 1 + lc.merge_passes; break;
+        }
+    }
+    out->bytes_moved = (double)out->passes * 2.0 * (double)lc.n * (double)lc.es;
+    return SR_OK;
+}
+
+const char* sr_status_str(sr_status s) {
+    switch (s) {
+    case SR_OK: return "ok";
+    case SR_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SR_ERR_UNSUPPORTED: return "unsupported";
+    case SR_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SR_ERR_DEVICE: return "device error";
+    case SR_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* sr_last_error_message(void) { return g_err.c_str(); }
+
+sr_status sr_set_option(const char* name, int64_t value) {
+    g_err.clear();
+    if (!name) return fail(SR_ERR_INVALID_ARGUMENT, "name is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (std::strcmp(name, "force_path") == 0) {
+        if (value < -1 || value > SR_PATH_GENERAL) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
+        g_force_path = (int)value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "profile") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "profile is 0 or 1");
+        g_profile = value != 0;
+        return SR_OK;
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, std::string("unknown option ") + name);
+}
+
+sr_status sr_profile_collect(const char* prefix, int64_t* launches, double* total_ms) {
+    g_err.clear();
+    if (!launches || !total_ms) return fail(SR_ERR_INVALID_ARGUMENT, "NULL output");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        recs.swap(g_prof);
+    }
+    const size_t pl = prefix ? std::strlen(prefix) : 0;
+    int64_t cnt = 0;
+    double ms = 0;
+    sr_status st = SR_OK;
+    for (auto& r : recs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess && st == SR_OK) st = hip_fail(e, "hipEventSynchronize");
+        if (pl == 0 || r.name.compare(0, pl, prefix) == 0) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms += t;
+                cnt++;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& r : recs) {
+            g_event_pool.push_back(r.a);
+            g_event_pool.push_back(r.b);
+        }
+    }
+    *launches = cnt;
+    *total_ms = ms;
+    return st;
+}
+
+sr_status sr_copy_bandwidth_probe(void* dst, const void* src, size_t bytes, void* stream) {
+    g_err.clear();
+    if (!dst || !src || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(SR_ERR_INVALID_ARGUMENT, "copy probe needs 16-byte aligned buffers and size");
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return SR_OK;
+    ProfScope ps((hipStream_t)stream, "copy16");
+    const unsigned g = (unsigned)std::min<int64_t>(cdiv(n16, 256 * 4), 65536);
+    hipLaunchKernelGGL(k_copy16, dim3(g), dim3(256), 0, (hipStream_t)stream, (uint4*)dst, (const uint4*)src, n16);
+    SR_LAUNCH_CHECK("copy16");
+    return SR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// sr_kernels.hpp -- the sort-path kernels of libsortrace as device functions
+// plus thin __global__ wrappers.  Included by the engine translation unit.
+//
+// Pass structure (general path): a tile sort sorts every tile of T keys
+// inside one workgroup (the GPU form of the paper's base case, Sec. 3 (b):
+// short runs are extended to a minimum length before merging), then
+// level-synchronous merge passes pair up neighbouring sorted runs, all pairs
+// of a level in one launch (Sec. 3 (e1): in each round all runs are paired
+// and merged).  Each merge pass cuts its output into chunks by Merge Path, so
+// the work per workgroup is equal whatever the data.
+#pragma once
+
+#include <type_traits>
+
+#include "sr_device.hpp"
+
+namespace sr {
+
+// 16-byte vector of storage elements, for dwordx4 loads and stores.
+template <class S>
+struct alignas(16) V16 {
+    S v[16 / sizeof(S)];
+};
+
+__device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+    return x;
+}
+
+// ==================================================================== tile
+// Sorts one tile of `valid` (<= WG*IT) keys from src into dst (src may equal
+// dst).  Keys-only: wavefront bitonic sort of 64*IT keys in registers, then
+// Merge Path merges in LDS across the WG/64 wavefronts.  Pairs: the same on
+// (key, tile position) elements, so the result is the stable order, and the
+// payload is gathered by position at the end.
+template <class C, int WG, int IT, bool PAIRS>
+struct TileSort {
+    using S = typename C::S;
+    using U = typename C::U;
+    static constexpr int T = WG * IT;
+    static constexpr int VN = 16 / sizeof(S);
+    static_assert(IT % VN == 0, "IT must hold whole 16-byte vectors");
+    static_assert(WG % kWave == 0, "whole wavefronts");
+
+    struct Smem {
+        U k[T];
+        uint32_t p[PAIRS ? T : 1];     // tile position of each element
+        uint32_t pay[PAIRS ? T : 1];   // payload, by tile position
+    };
+
+    using E = typename std::conditional<PAIRS, KeyPos<U>, U>::type;
+
+    static __device__ __forceinline__ E make(U k, uint32_t pos) {
+        if constexpr (PAIRS) return KeyPos<U>{k, pos};
+        else return k;
+    }
+    static __device__ __forceinline__ U key_of(const E& e) {
+        if constexpr (PAIRS) return e.k;
+        else return e;
+    }
+
+    static __device__ __forceinline__ bool before(U ka, uint32_t pa, U kb, uint32_t pb) {
+        if constexpr (PAIRS) return ka < kb || (ka == kb && pa < pb);
+        else return ka < kb;
+    }
+
+    // One merge level in LDS: runs of `width` become runs of 2*width.  The
+    // thread produces outputs [tid*IT, tid*IT + IT) of its 2*width group.
+    static __device__ __forceinline__ void lds_level(const Smem& sm, int width, int tid, E (&v)[IT]) {
+        const int out0 = tid * IT;
+        const int gs = out0 & ~(2 * width - 1);
+        const int d = out0 - gs;
+        const U* A = sm.k + gs;
+        const U* B = A + width;
+        int lo = d > width ? d - width : 0;
+        int hi = d < width ? d : width;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            bool a_first;
+            if constexpr (PAIRS) a_first = !before(B[d - 1 - mid], sm.p[gs + width + d - 1 - mid], A[mid], sm.p[gs + mid]);
+            else a_first = A[mid] <= B[d - 1 - mid];
+            if (a_first) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = d - lo;
+        int ia = gs + (i < width ? i : width - 1);
+        int ib = gs + width + (j < width ? j : width - 1);
+        U a = sm.k[ia], b = sm.k[ib];
+        uint32_t pa = 0, pb = 0;
+        if constexpr (PAIRS) {
+            pa = sm.p[ia];
+            pb = sm.p[ib];
+        }
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const bool ta = (j >= width) || (i < width && !before(b, pb, a, pa));
+            if constexpr (PAIRS) v[r] = make(ta ? a : b, ta ? pa : pb);
+            else v[r] = ta ? a : b;
+            i += ta ? 1 : 0;
+            j += ta ? 0 : 1;
+            const int nx = ta ? gs + (i < width ? i : width - 1) : gs + width + (j < width ? j : width - 1);
+            const U kn = sm.k[nx];
+            a = ta ? kn : a;
+            b = ta ? b : kn;
+            if constexpr (PAIRS) {
+                const uint32_t pn = sm.p[nx];
+                pa = ta ? pn : pa;
+                pb = ta ? pb : pn;
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void put(Smem& sm, int tid, const E (&v)[IT]) {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            if constexpr (PAIRS) {
+                sm.k[tid * IT + r] = v[r].k;
+                sm.p[tid * IT + r] = v[r].p;
+            } else {
+                sm.k[tid * IT + r] = v[r];
+            }
+        }
+    }
+
+    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid) {
+        const int tid = threadIdx.x;
+        E v[IT];
+        const bool vec = valid == T && aligned16(src) && (!PAIRS || aligned16(psrc));
+        if (vec) {
+#pragma unroll
+            for (int q = 0; q < IT / VN; ++q) {
+                const int e0 = (tid + q * WG) * VN;
+                const V16<S> x = reinterpret_cast<const V16<S>*>(src)[tid + q * WG];
+#pragma unroll
+                for (int j = 0; j < VN; ++j) v[q * VN + j] = make(C::enc(x.v[j]), (uint32_t)(e0 + j));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const int e = tid + r * WG;
+                v[r] = make(e < valid ? C::enc(src[e]) : key_max<U>(), (uint32_t)e);
+            }
+        }
+        if constexpr (PAIRS) {
+            for (int e = tid; e < valid; e += WG) sm.pay[e] = psrc[e];
+        }
+
+        wave_sort(v);
+
+        if constexpr (T > kWave * IT) {
+            put(sm, tid, v);
+#pragma unroll 1
+            for (int width = kWave * IT; width < T; width *= 2) {
+                __syncthreads();
+                lds_level(sm, width, tid, v);
+                __syncthreads();
+                put(sm, tid, v);
+            }
+        } else {
+            put(sm, tid, v);
+        }
+        __syncthreads();
+
+        // store, striped so that consecutive lanes write consecutive addresses
+        const bool vout = valid == T && aligned16(dst);
+        if (vout) {
+#pragma unroll
+            for (int q = 0; q < IT / VN; ++q) {
+                const int e0 = (tid + q * WG) * VN;
+                V16<S> x;
+#pragma unroll
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[e0 + j]);
+                reinterpret_cast<V16<S>*>(dst)[tid + q * WG] = x;
+            }
+        } else {
+            for (int e = tid; e < valid; e += WG) dst[e] = C::dec(sm.k[e]);
+        }
+        if constexpr (PAIRS) {
+            for (int e = tid; e < valid; e += WG) pdst[e] = sm.pay[sm.p[e]];
+        }
+    }
+};
+
+// ================================================================== merge
+// One output chunk of WG*IT keys of one merge pass: the runs A = [gs, gs+w)
+// and B = [gs+w, gs+2w) of src (clipped to n) are merged into dst[gs, ...).
+// The chunk's input windows come from two Merge Path searches (wavefronts 0
+// and 1), are staged in LDS, and every thread merges IT outputs serially
+// after its own co-rank search inside LDS.  Ties take A: stable.
+template <class C, int WG, int IT, bool PAIRS>
+struct MergeChunk {
+    using S = typename C::S;
+    using U = typename C::U;
+    static constexpr int CH = WG * IT;
+    static constexpr int VN = 16 / sizeof(S);
+    static_assert(WG >= 2 * kWave, "two wavefronts search the window bounds");
+
+    struct Smem {
+        U k[CH];
+        uint32_t pay[PAIRS ? CH : 1];
+        int64_t co[2];
+    };
+
+    // src/dst/psrc/pdst point at the start of the (segment) array of length n.
+    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
+                               int64_t n, int64_t width, int64_t out0) {
+        const int tid = threadIdx.x;
+        const int64_t gs = out0 / (2 * width) * (2 * width);
+        const int64_t la = (n - gs) < width ? (n - gs) : width;
+        const int64_t rest = n - gs - la;
+        const int64_t lb = rest < width ? rest : width;
+        const int64_t d0 = out0 - gs;
+        const int64_t d1 = (d0 + CH) < (la + lb) ? (d0 + CH) : (la + lb);
+        const S* A = src + gs;
+        const S* B = A + la;
+        const int wave = tid / kWave;
+        if (wave < 2) {
+            const int64_t c = corank_wave<C>(A, la, B, lb, wave == 0 ? d0 : d1);
+            if (__lane_id() == 0) sm.co[wave] = c;
+        }
+        __syncthreads();
+        const int64_t i0 = sm.co[0], i1 = sm.co[1];
+        const int64_t j0 = d0 - i0, j1 = d1 - i1;
+        const int na = (int)(i1 - i0), nb = (int)(j1 - j0);
+        const int cnt = na + nb;
+        for (int e = tid; e < cnt; e += WG) {
+            const bool fa = e < na;
+            const int64_t gi = fa ? gs + i0 + e : gs + la + j0 + (e - na);
+            sm.k[e] = C::enc(src[gi]);
+            if constexpr (PAIRS) sm.pay[e] = psrc[gi];
+        }
+        __syncthreads();
+
+        const int t0 = tid * IT;
+        U v[IT];
+        uint32_t pv[IT];
+        if (t0 < cnt) {
+            const U* Aw = sm.k;
+            const U* Bw = sm.k + na;
+            int i = corank_lds(Aw, na, Bw, nb, t0);
+            int j = t0 - i;
+            const int last = cnt - 1;
+            int ia = i < na ? i : last;
+            int ib = na + (j < nb ? j : nb - 1);
+            ib = ib < 0 ? 0 : ib;
+            U a = sm.k[ia], b = sm.k[ib];
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const bool ta = (j >= nb) || (i < na && a <= b);
+                v[r] = ta ? a : b;
+                if constexpr (PAIRS) pv[r] = sm.pay[ta ? (i < na ? i : last) : (na + j < cnt ? na + j : last)];
+                i += ta ? 1 : 0;
+                j += ta ? 0 : 1;
+                int nx = ta ? i : na + j;
+                nx = nx < last ? nx : last;
+                const U kn = sm.k[nx];
+                a = ta ? kn : a;
+                b = ta ? b : kn;
+            }
+        }
+        __syncthreads();
+        if (t0 < cnt) {
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                if (t0 + r < cnt) {
+                    sm.k[t0 + r] = v[r];
+                    if constexpr (PAIRS) sm.pay[t0 + r] = pv[r];
+                }
+            }
+        }
+        __syncthreads();
+        S* out = dst + out0;
+        if (cnt == CH && aligned16(out)) {
+#pragma unroll
+            for (int q = 0; q < IT / VN; ++q) {
+                const int e0 = (tid + q * WG) * VN;
+                V16<S> x;
+#pragma unroll
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[e0 + j]);
+                reinterpret_cast<V16<S>*>(out)[tid + q * WG] = x;
+            }
+        } else {
+            for (int e = tid; e < cnt; e += WG) out[e] = C::dec(sm.k[e]);
+        }
+        if constexpr (PAIRS) {
+            uint32_t* pout = pdst + out0;
+            for (int e = tid; e < cnt; e += WG) pout[e] = sm.pay[e];
+        }
+    }
+};
+
+}  // namespace sr

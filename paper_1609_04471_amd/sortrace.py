@@ -1,0 +1,201 @@
+"""Thin ctypes binding of libsortrace.so (argument marshalling only).
+
+Every sort runs in the HIP kernels of ``libsortrace.so``; this module only
+passes device pointers, sizes and the torch stream handle through the C ABI
+declared in ``include/sortrace.h``.  There is no fallback: if the library is
+missing, ``load()`` raises.
+
+Tensors must be CUDA (HIP) tensors, contiguous.  int32 and float32 tensors
+map to SR_INT32 / SR_FLOAT32; uint64 keys are passed as torch.uint64 or as an
+int64 tensor with ``dtype="uint64"`` (same bits).  Payloads are int32 or
+uint32 tensors carrying uint32 values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsortrace.so")
+
+SR_INT32, SR_UINT64, SR_FLOAT32 = 0, 1, 2
+DTYPES = {"int32": SR_INT32, "uint64": SR_UINT64, "float32": SR_FLOAT32}
+PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general"}
+STATUS = {0: "SR_OK", 1: "SR_ERR_INVALID_ARGUMENT", 2: "SR_ERR_UNSUPPORTED",
+          3: "SR_ERR_OUT_OF_MEMORY", 4: "SR_ERR_DEVICE", 5: "SR_ERR_INTERNAL"}
+
+# Every symbol include/sortrace.h declares.
+EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_measure",
+           "sr_workspace_bytes", "sr_last_stats", "sr_status_str", "sr_last_error_message",
+           "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe")
+
+
+class SrStats(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("passes", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("descents", ctypes.c_int64), ("outliers", ctypes.c_int64),
+                ("bytes_moved", ctypes.c_double)]
+
+
+class SortraceError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsortrace.so (torch first, so its HIP runtime is the one used)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the process's HIP runtime)
+    if not os.path.exists(path):
+        raise RuntimeError(f"libsortrace.so is not built ({path}); run "
+                           "`python -m paper_1609_04471_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64
+    lib.sr_sort_keys.argtypes = [i32, vp, sz, vp]
+    lib.sr_sort_pairs.argtypes = [i32, vp, vp, sz, vp]
+    lib.sr_sort_segmented.argtypes = [i32, vp, vp, sz, vp, sz, vp]
+    lib.sr_measure.argtypes = [i32, vp, sz, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.sr_workspace_bytes.argtypes = [i32, i32, sz, sz, ctypes.POINTER(ctypes.c_size_t)]
+    lib.sr_last_stats.argtypes = [vp, ctypes.POINTER(SrStats)]
+    lib.sr_status_str.argtypes = [i32]
+    lib.sr_status_str.restype = ctypes.c_char_p
+    lib.sr_last_error_message.argtypes = []
+    lib.sr_last_error_message.restype = ctypes.c_char_p
+    lib.sr_set_option.argtypes = [ctypes.c_char_p, i64]
+    lib.sr_profile_collect.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]
+    lib.sr_copy_bandwidth_probe.argtypes = [vp, vp, sz, vp]
+    for name in EXPORTS:
+        if name not in ("sr_status_str", "sr_last_error_message"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = _lib.sr_last_error_message().decode(errors="replace")
+        raise SortraceError(rc, what, msg)
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _key_dtype(t, dtype: str | None) -> int:
+    import torch
+    if dtype is not None:
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        want = {"int32": 4, "float32": 4, "uint64": 8}[dtype]
+        if t.element_size() != want:
+            raise ValueError(f"{dtype} keys need {want}-byte elements, got {t.dtype}")
+        return DTYPES[dtype]
+    if t.dtype == torch.int32:
+        return SR_INT32
+    if t.dtype == torch.float32:
+        return SR_FLOAT32
+    if t.dtype == getattr(torch, "uint64", None):
+        return SR_UINT64
+    raise ValueError(f"key dtype {t.dtype} needs an explicit dtype= (int32, uint64, float32)")
+
+
+def _dev(t, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+def sort_keys(keys, dtype: str | None = None, stream=None):
+    """Sort ``keys`` in place (ascending; float32 by totalOrder). Returns keys."""
+    lib = load()
+    dt = _key_dtype(keys, dtype)
+    _check(lib.sr_sort_keys(dt, _dev(keys, "keys"), keys.numel(), _stream(stream)), "sr_sort_keys")
+    return keys
+
+
+def sort_pairs(keys, payload, dtype: str | None = None, stream=None):
+    """Stable in-place sort of (key, uint32 payload). Returns (keys, payload)."""
+    lib = load()
+    dt = _key_dtype(keys, dtype)
+    if payload.numel() != keys.numel() or payload.element_size() != 4:
+        raise ValueError("payload must hold one 4-byte value per key")
+    _check(lib.sr_sort_pairs(dt, _dev(keys, "keys"), _dev(payload, "payload"), keys.numel(),
+                             _stream(stream)), "sr_sort_pairs")
+    return keys, payload
+
+
+def sort_segmented(keys, offsets, payload=None, dtype: str | None = None, stream=None):
+    """Sort every CSR segment [offsets[s], offsets[s+1]) of keys in place."""
+    import torch
+    lib = load()
+    dt = _key_dtype(keys, dtype)
+    if offsets.dtype != torch.int64:
+        raise ValueError("offsets must be int64")
+    pp = None
+    if payload is not None:
+        if payload.numel() != keys.numel() or payload.element_size() != 4:
+            raise ValueError("payload must hold one 4-byte value per key")
+        pp = _dev(payload, "payload")
+    nseg = offsets.numel() - 1
+    _check(lib.sr_sort_segmented(dt, _dev(keys, "keys"), pp, keys.numel(), _dev(offsets, "offsets"),
+                                 max(nseg, 0), _stream(stream)), "sr_sort_segmented")
+    return keys if payload is None else (keys, payload)
+
+
+def measure(keys, dtype: str | None = None, stream=None):
+    """(descents, ascents) of keys; Run(A) = descents + 1.  Synchronizes."""
+    lib = load()
+    out = (ctypes.c_int64 * 2)()
+    _check(lib.sr_measure(_key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(), out,
+                          _stream(stream)), "sr_measure")
+    return int(out[0]), int(out[1])
+
+
+def last_stats(stream=None) -> dict:
+    """Path, passes and bytes of the last sort on the stream.  Synchronizes."""
+    lib = load()
+    s = SrStats()
+    _check(lib.sr_last_stats(_stream(stream), ctypes.byref(s)), "sr_last_stats")
+    return {"path": PATHS.get(s.path, s.path), "passes": s.passes, "n": s.n,
+            "descents": s.descents, "outliers": s.outliers, "bytes_moved": s.bytes_moved}
+
+
+def workspace_bytes(dtype: str, with_payload: bool, n: int, nseg: int = 0) -> int:
+    lib = load()
+    b = ctypes.c_size_t()
+    _check(lib.sr_workspace_bytes(DTYPES[dtype], int(with_payload), n, nseg, ctypes.byref(b)),
+           "sr_workspace_bytes")
+    return b.value
+
+
+def set_option(name: str, value: int) -> None:
+    lib = load()
+    _check(lib.sr_set_option(name.encode(), int(value)), "sr_set_option")
+
+
+def profile_collect(prefix: str = ""):
+    """(launches, total_ms) of recorded kernels whose name starts with prefix."""
+    lib = load()
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib.sr_profile_collect(prefix.encode(), ctypes.byref(n), ctypes.byref(ms)),
+           "sr_profile_collect")
+    return n.value, ms.value
+
+
+def copy_probe(dst, src, stream=None) -> None:
+    lib = load()
+    nbytes = src.numel() * src.element_size()
+    _check(lib.sr_copy_bandwidth_probe(_dev(dst, "dst"), _dev(src, "src"), nbytes, _stream(stream)),
+           "sr_copy_bandwidth_probe")
