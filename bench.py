@@ -1,0 +1,281 @@
+"""Benchmark of libsortrace on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-big] [--no-cpu]
+
+Workload (the step): plain in-place int32 sorts of n = 2,000,000 keys, one of
+each of the four input types of Table 1 of the Sort Race paper (random,
+reversely sorted, nearly sorted, few unique), inputs already resident in HBM.
+``value`` is the aggregate Mkeys/s over the K timed steps (4 x 2M keys each).
+
+Besides the JSON fields of the contract the line carries:
+  per_type_2M / per_type_256M   Mkeys/s, path and passes per input type
+  roofline      the dominant kernel (merge pass) on 256M random int32 keys:
+                algorithmic bytes per launch (2 x n x 4) / mean launch time
+                measured with HIP events on the launch stream, against 8 TB/s
+  copy_GBps     a 16-byte copy kernel's rate in the same run (practical peak)
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+                same workload
+Data is synthetic (seeded generators in paper_1609_04471_amd.inputs).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mkeys/s int32 sort at n=2M (4 input types), %HBM roofline; batched p99 ms"
+PEAK_HBM_GBPS = 8000.0
+N_SMALL = 2_000_000
+N_BIG = 268_435_456
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1609_04471_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_sha") != kernel_source_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=10, help="timed reps per type at 256M")
+    ap.add_argument("--no-big", action="store_true", help="skip the n=256M section")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["small", "big-random"], default=None,
+                    help="run one section only (for profiler runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build sorts on one GPU; a run over several GPUs is not part of it "
+              "(see DESIGN.md for how the sort would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1609_04471_amd import inputs, sortrace
+
+    sortrace.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    types = list(inputs.TYPES)
+
+    def host_input(kind, n):
+        return inputs.int32_of_type(kind, n, inputs.seed_for(2, types.index(kind), n))
+
+    result = {}
+
+    # ------------------------------------------------------------ step: 4 x 2M
+    if args.only in (None, "small"):
+        log("generating 2M inputs")
+        pristine = {k: torch.from_numpy(host_input(k, N_SMALL)).to(dev) for k in types}
+        total_steps = args.warmup + args.steps
+        bufs = [{k: pristine[k].clone() for k in types} for _ in range(total_steps)]
+        torch.cuda.synchronize()
+        for s in range(args.warmup):
+            for k in types:
+                sortrace.sort_keys(bufs[s][k])
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for s in range(args.warmup, total_steps):
+            for k in types:
+                sortrace.sort_keys(bufs[s][k])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        ms_per_step = gpu_ms / args.steps
+        value = args.steps * len(types) * N_SMALL / (gpu_ms / 1e3) / 1e6
+        log(f"step: {ms_per_step:.4f} ms (wall {wall * 1e3 / args.steps:.4f} ms) -> {value:.1f} Mkeys/s")
+        # correctness of the timed outputs (cheap property: nondecreasing)
+        for k in types:
+            b = bufs[-1][k]
+            assert bool((b[1:] >= b[:-1]).all()), k
+        del bufs
+
+        per_small = {}
+        for k in types:
+            reps = 30
+            work = [pristine[k].clone() for _ in range(reps + 3)]
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(reps)]
+            torch.cuda.synchronize()
+            for i in range(3):
+                sortrace.sort_keys(work[i])
+            for i in range(reps):
+                evs[i][0].record(stream)
+                sortrace.sort_keys(work[3 + i])
+                evs[i][1].record(stream)
+            torch.cuda.synchronize()
+            times = [a.elapsed_time(b) for a, b in evs]
+            st = sortrace.last_stats()
+            med = statistics.median(times)
+            per_small[k] = {"ms_median": round(med, 5), "ms_min": round(min(times), 5),
+                            "Mkeys_s": round(N_SMALL / (med / 1e3) / 1e6, 1),
+                            "path": st["path"], "passes": st["passes"]}
+            log(f"2M {k}: {per_small[k]}")
+            del work
+        result.update(value=value, ms_per_step=ms_per_step, per_type_2M=per_small)
+        del pristine
+
+    # ------------------------------------------------------------ 256M section
+    roofline = None
+    per_big = {}
+    copy_gbps = None
+    if not args.no_big and args.only in (None, "big-random"):
+        big_types = types if args.only is None else ["random"]
+        work = torch.empty(N_BIG, dtype=torch.int32, device=dev)
+        # bandwidth reference: 16-byte copy of 1 GiB
+        src = torch.empty(N_BIG, dtype=torch.int32, device=dev)
+        sortrace.copy_probe(src, work)
+        torch.cuda.synchronize()
+        cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for a, b in cev:
+            a.record(stream)
+            sortrace.copy_probe(src, work)
+            b.record(stream)
+        torch.cuda.synchronize()
+        cms = statistics.median([a.elapsed_time(b) for a, b in cev])
+        copy_gbps = 2 * N_BIG * 4 / (cms / 1e3) / 1e9
+        log(f"copy16: {copy_gbps:.0f} GB/s")
+        for k in big_types:
+            log(f"generating 256M {k}")
+            h = host_input(k, N_BIG)
+            src.copy_(torch.from_numpy(h))
+            del h
+            times = []
+            for i in range(args.reps + 1):
+                work.copy_(src)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                sortrace.sort_keys(work)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if i > 0:
+                    times.append(a.elapsed_time(b))
+            st = sortrace.last_stats()
+            assert bool((work[1:] >= work[:-1]).all()), k
+            med = statistics.median(times)
+            per_big[k] = {"ms_median": round(med, 4), "ms_min": round(min(times), 4),
+                          "Mkeys_s": round(N_BIG / (med / 1e3) / 1e6, 1),
+                          "path": st["path"], "passes": st["passes"],
+                          "algorithmic_GBps": round(st["passes"] * 2 * N_BIG * 4 / (med / 1e3) / 1e9, 1)}
+            log(f"256M {k}: {per_big[k]}")
+            if k == "random":
+                # per-kernel times with HIP events on the launch stream
+                sortrace.set_option("profile", 1)
+                sortrace.profile_collect("")
+                for _ in range(3):
+                    work.copy_(src)
+                    sortrace.sort_keys(work)
+                torch.cuda.synchronize()
+                kern = {}
+                for name in ("probe", "tile_sort", "partition", "merge"):
+                    cnt, ms = sortrace.profile_collect(name)
+                    kern[name] = (cnt, ms)
+                sortrace.set_option("profile", 0)
+                mcnt, mms = kern["merge"]
+                avg_ms = mms / max(mcnt, 1)
+                alg_bytes = 2 * N_BIG * 4
+                achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+                tcnt, tms = kern["tile_sort"]
+                roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                            "traffic": measured_traffic("merge_int32_256M"),
+                            "kernel": "merge pass (k_merge int32, 256x16 outputs per workgroup)",
+                            "workload": "int32 random n=268435456",
+                            "launch_ms_mean": round(avg_ms, 5), "launches": mcnt,
+                            "algorithmic_bytes_per_launch": alg_bytes,
+                            "partition_ms_mean": round(kern["partition"][1] / max(kern["partition"][0], 1), 5),
+                            "probe_ms_mean": round(kern["probe"][1] / max(kern["probe"][0], 1), 5),
+                            "tile_sort_ms_mean": round(tms / max(tcnt, 1), 5),
+                            "tile_sort_GBps": round(alg_bytes / (tms / max(tcnt, 1) / 1e3) / 1e9, 1)}
+                log(f"roofline: {roofline}")
+        del work, src
+        torch.cuda.synchronize()
+    result.update(per_type_256M=per_big or None, roofline=roofline, copy_GBps=round(copy_gbps, 1) if copy_gbps else None)
+
+    # ------------------------------------------------------------ CPU baseline
+    cpu = None
+    if not args.no_cpu and args.only is None:
+        import oracle
+        hosts = {k: host_input(k, N_SMALL) for k in types}
+        done, t0 = 0, time.perf_counter()
+        rounds = 0
+        while True:
+            for k in types:
+                oracle.sort_keys(hosts[k])
+                done += N_SMALL
+            rounds += 1
+            el = time.perf_counter() - t0
+            if el > 10.0 or rounds >= 8:
+                break
+        cpu = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"{rounds} round(s) of the four 2M int32 inputs ({done} keys) through the "
+                         f"single-threaded oracle mergesort, {el:.1f} s"}
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": METRIC,
+        "value": round(result.get("value", 0.0), 1),
+        "unit": "Mkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(result.get("ms_per_step", 0.0), 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "plain in-place int32 sort, n=2,000,000 keys, four input types "
+                               "(random, reversed, nearly sorted, few unique), keys only",
+                   "n": N_SMALL, "arrays_per_step": len(types), "types": types},
+        "roofline": result.get("roofline"),
+        "cpu_baseline": cpu,
+        "per_type_2M": result.get("per_type_2M"),
+        "per_type_256M": result.get("per_type_256M"),
+        "copy_GBps": result.get("copy_GBps"),
+        "gpu": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

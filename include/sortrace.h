@@ -127,17 +127,20 @@ const char *sr_last_error_message(void);
  *                 (SR_PATH_GENERAL is always safe).
  *   "profile"     1 = record a HIP event pair around every kernel the sort
  *                 path launches (on the caller's stream); 0 = off (default).
+ *   "partition_min_n"  from this n on, every merge pass is preceded by a
+ *                 separate Merge Path partition launch; below it each merge
+ *                 workgroup searches its own window bounds (default 2^22).
  * Returns SR_ERR_INVALID_ARGUMENT for an unknown name or value.
  */
 sr_status sr_set_option(const char *name, int64_t value);
 
 /*
  * With "profile" on: sums the device time of the recorded launches whose
- * kernel name starts with `prefix` ("" = all), then forgets every recorded
- * launch.  Synchronizes on the recorded events.  launches and total_ms are
- * host memory.  Kernel names: "probe", "reverse", "regroup", "tile_sort",
- * "merge", "classify", "merge_outliers", "seg_plan", "seg_tile_sort",
- * "seg_merge".
+ * kernel name starts with `prefix` ("" = all) and forgets those launches
+ * (the others stay recorded).  Synchronizes on the recorded events.  launches and total_ms are
+ * host memory.  Kernel names: "probe", "tile_sort" (also carries the
+ * reversal), "regroup", "partition", "merge", "classify", "merge_outliers",
+ * "seg_plan", "seg_tile_sort", "seg_merge".
  */
 sr_status sr_profile_collect(const char *prefix, int64_t *launches, double *total_ms);
 

@@ -266,6 +266,22 @@ __device__ __forceinline__ int corank_lds(const U* A, int la, const U* B, int lb
     return lo;
 }
 
+// The same search by a single thread in global memory (plain binary search).
+template <class C>
+__device__ __forceinline__ int64_t corank_thread(const typename C::S* A, int64_t la,
+                                                 const typename C::S* B, int64_t lb, int64_t d) {
+    int64_t lo = d > lb ? d - lb : 0;
+    int64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (C::enc(A[mid]) <= C::enc(B[d - 1 - mid]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Same search in global memory by one whole wavefront: each round the 64
 // lanes test 64 evenly spaced candidates, so the range shrinks 64-fold per
 // round.  Keys are decoded with codec C on load.  Returns the co-rank in all

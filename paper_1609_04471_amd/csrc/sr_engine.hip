@@ -55,6 +55,7 @@ constexpr int kProbeWG = 256;
 constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
 constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
 constexpr int kRevWG = 256;
+constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over its tiles)
 
 __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
     return ctl == nullptr || ld_agent(&ctl->path) == want;
@@ -62,90 +63,232 @@ __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
 
 // ============================================================== kernels
 
+// Tile sort of the GENERAL path.  The same launch carries the REVERSED path:
+// then workgroup b swaps the pairs (i, n-1-i) for i in its half-tile share
+// [b*T/2, (b+1)*T/2) of [0, n/2), in place in `keys`.
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_tile_sort(const typename C::S* src, typename C::S* dst,
                                                   const uint32_t* psrc, uint32_t* pdst, int64_t n,
-                                                  const Ctl* ctl, int need) {
+                                                  const Ctl* ctl, int need, typename C::S* keys,
+                                                  uint32_t* pay) {
     using TS = TileSort<C, WG, IT, PAIRS>;
-    if (!path_is(ctl, need)) return;
+    using S = typename C::S;
+    if (ctl != nullptr) {
+        const int path = ld_agent(&ctl->path);
+        if (path == SR_PATH_REVERSED) {
+            constexpr int H = TS::T / 2;
+            constexpr int R = H / WG;
+            const int64_t half = n / 2;
+            const int64_t i0 = (int64_t)blockIdx.x * H + threadIdx.x;
+            S a[R], b[R];
+            uint32_t pa[R], pb[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = i0 + (int64_t)r * WG;
+                if (i < half) {
+                    a[r] = keys[i];
+                    b[r] = keys[n - 1 - i];
+                    if constexpr (PAIRS) {
+                        pa[r] = pay[i];
+                        pb[r] = pay[n - 1 - i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = i0 + (int64_t)r * WG;
+                if (i < half) {
+                    keys[i] = b[r];
+                    keys[n - 1 - i] = a[r];
+                    if constexpr (PAIRS) {
+                        pay[i] = pb[r];
+                        pay[n - 1 - i] = pa[r];
+                    }
+                }
+            }
+            return;
+        }
+        if (path != need) return;
+    }
     __shared__ typename TS::Smem sm;
     const int64_t base = (int64_t)blockIdx.x * TS::T;
     const int valid = (int)((n - base) < TS::T ? (n - base) : TS::T);
     TS::run(sm, src + base, dst + base, PAIRS ? psrc + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
 }
 
+// Merge Path partition of one merge pass: co[c] = co-rank of the start of
+// output chunk c (c*CH) inside its pair of runs.  One thread per chunk.
+template <class C>
+__global__ __launch_bounds__(256) void k_partition(const typename C::S* src, int64_t n, int64_t width,
+                                                   int CH, int64_t nchunks, int64_t* co, const Ctl* ctl,
+                                                   int need) {
+    if (!path_is(ctl, need)) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nchunks) return;
+    const int64_t out0 = c * CH;
+    const int64_t gs = out0 / (2 * width) * (2 * width);
+    const int64_t la = (n - gs) < width ? (n - gs) : width;
+    const int64_t rest = n - gs - la;
+    const int64_t lb = rest < width ? rest : width;
+    co[c] = corank_thread<C>(src + gs, la, src + gs + la, lb, out0 - gs);
+}
+
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge(const typename C::S* src, typename C::S* dst,
                                               const uint32_t* psrc, uint32_t* pdst, int64_t n,
-                                              int64_t width, const Ctl* ctl, int need) {
+                                              int64_t width, const Ctl* ctl, int need, const int64_t* co) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     if (!path_is(ctl, need)) return;
     __shared__ typename MC::Smem sm;
-    MC::run(sm, src, dst, psrc, pdst, n, width, (int64_t)blockIdx.x * MC::CH);
+    MC::run(sm, src, dst, psrc, pdst, n, width, (int64_t)blockIdx.x * MC::CH, co);
 }
 
-// Probe: workgroup b owns the neighbour pairs (i, i+1) for i in
-// [b*kProbeTile, (b+1)*kProbeTile) and i+1 < n.  The last workgroup to finish
-// turns the counters into the plan and clears them.
+template <class C, int WG, int IT, bool PAIRS>
+__global__ __launch_bounds__(WG) void k_merge_persist(const typename C::S* src, typename C::S* dst,
+                                                      const uint32_t* psrc, uint32_t* pdst, int64_t n,
+                                                      int64_t width, const Ctl* ctl, int need, const int64_t* co,
+                                                      int64_t nchunks) {
+    using MP = MergePersistent<C, WG, IT, PAIRS>;
+    if (!path_is(ctl, need)) return;
+    __shared__ typename MP::Smem sm;
+    MP::run(sm, src, dst, psrc, pdst, n, width, co, nchunks);
+}
+
+// Probe.  The array's neighbour pairs (i, i+1) are cut into probe tiles of
+// kProbeTile pairs; a capped grid walks them grid-stride.  Before each tile a
+// workgroup checks the global "mixed" flag and stops once some workgroup has
+// seen both an ascent and a descent (then the array is neither sorted nor
+// reversed).  Each workgroup also samples kProbeSample pairs at an evenly
+// spread position for the descent-rate estimate.  The last workgroup to
+// finish turns the counters into the plan and clears them.
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
-                                                    int outlier_ok) {
+                                                    unsigned long long* slots, int outlier_ok) {
     using U = typename C::U;
+    using S = typename C::S;
+    constexpr int VN = 16 / sizeof(S);
+    constexpr int Q = (int)(kProbeTile / (kProbeWG * VN));  // vectors per thread per tile
     __shared__ unsigned long long red[4][kProbeWG / kWave];
     __shared__ int skip;
     __shared__ unsigned int last;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
-    const int64_t b0 = (int64_t)blockIdx.x * kProbeTile;
-    const int64_t b1 = std::min<int64_t>(b0 + kProbeTile, n - 1);
-    if (tid == 0) skip = ld_agent(&ctl->mixed) != 0;
+    const int64_t npairs = n - 1;
+    const int64_t ntiles = (npairs + kProbeTile - 1) / kProbeTile;
 
+    // sample: kProbeSample pairs at the start of tile blockIdx * ntiles / gridDim
     unsigned long long sd = 0, sp = 0;
-    const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, b1);
-    for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
-        const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
-        sd += x > y ? 1 : 0;
-        sp += 1;
-    }
-    __syncthreads();
-    unsigned long long d = 0, a = 0;
-    if (!skip) {
-        for (int64_t i = b0 + tid; i < b1; i += kProbeWG) {
+    {
+        const int64_t t = (int64_t)blockIdx.x * ntiles / gridDim.x;
+        const int64_t b0 = t * kProbeTile;
+        const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, npairs);
+        for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
-            d += x > y ? 1 : 0;
-            a += x < y ? 1 : 0;
+            sd += x > y ? 1 : 0;
+            sp += 1;
         }
     }
-    d = wave_sum(d);
-    a = wave_sum(a);
+    unsigned long long d = 0, a = 0;
+    const bool vec_ok = aligned16(keys);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        __syncthreads();
+        if (tid == 0) skip = ld_agent(&ctl->mixed) != 0;
+        __syncthreads();
+        if (skip) break;
+        const int64_t b0 = t * kProbeTile;
+        const int64_t b1 = std::min<int64_t>(b0 + kProbeTile, npairs);
+        unsigned long long td = 0, ta = 0;
+        if (vec_ok && b1 - b0 == kProbeTile) {
+            // thread owns vectors q: keys [b0 + (tid + q*WG)*VN, +VN) and the key after them
+            V16<S> x[Q];
+            S nx[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t e = b0 + (int64_t)(tid + q * kProbeWG) * VN;
+                x[q] = *reinterpret_cast<const V16<S>*>(keys + e);
+                nx[q] = keys[e + VN];  // e + VN <= b1 <= n - 1
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+#pragma unroll
+                for (int j = 0; j < VN; ++j) {
+                    const U u = C::enc(x[q].v[j]);
+                    const U w = C::enc(j + 1 < VN ? x[q].v[j + 1] : nx[q]);
+                    td += u > w ? 1 : 0;
+                    ta += u < w ? 1 : 0;
+                }
+            }
+        } else {
+            for (int64_t i = b0 + tid; i < b1; i += kProbeWG) {
+                const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+                td += x > y ? 1 : 0;
+                ta += x < y ? 1 : 0;
+            }
+        }
+        td = wave_sum(td);
+        ta = wave_sum(ta);
+        __syncthreads();
+        if (__lane_id() == 0) {
+            red[0][wave] = td;
+            red[1][wave] = ta;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long sdn = 0, san = 0;
+            for (int w = 0; w < kProbeWG / kWave; ++w) {
+                sdn += red[0][w];
+                san += red[1][w];
+            }
+            d += sdn;
+            a += san;
+            if (d && a) {
+                atomicOr(&ctl->mixed, 1u);
+                skip = 1;
+            }
+        }
+    }
+    __syncthreads();
     sd = wave_sum(sd);
     sp = wave_sum(sp);
     if (__lane_id() == 0) {
-        red[0][wave] = d;
-        red[1][wave] = a;
         red[2][wave] = sd;
         red[3][wave] = sp;
     }
     __syncthreads();
     if (tid == 0) {
-        unsigned long long t[4] = {0, 0, 0, 0};
-        for (int w = 0; w < kProbeWG / kWave; ++w)
-            for (int q = 0; q < 4; ++q) t[q] += red[q][w];
-        if (t[0]) atomicAdd(&ctl->desc, t[0]);
-        if (t[1]) atomicAdd(&ctl->asc, t[1]);
-        if (t[2]) atomicAdd(&ctl->sample_desc, t[2]);
-        if (t[3]) atomicAdd(&ctl->sample_pairs, t[3]);
-        if (t[0] && t[1]) atomicOr(&ctl->mixed, 1u);
+        unsigned long long t2 = 0, t3 = 0;
+        for (int w = 0; w < kProbeWG / kWave; ++w) {
+            t2 += red[2][w];
+            t3 += red[3][w];
+        }
+        // per-workgroup slot (plain stores, no contention), then one ticket
+        slots[blockIdx.x * 4 + 0] = d;
+        slots[blockIdx.x * 4 + 1] = a;
+        slots[blockIdx.x * 4 + 2] = t2;
+        slots[blockIdx.x * 4 + 3] = t3;
         __threadfence();
         last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (last && tid == 0) {
+    if (last) {
         __threadfence();
-        const unsigned long long desc = ld_agent(&ctl->desc);
-        const unsigned long long asc = ld_agent(&ctl->asc);
-        const unsigned long long sdesc = ld_agent(&ctl->sample_desc);
-        const unsigned long long spairs = ld_agent(&ctl->sample_pairs);
+        unsigned long long acc[4] = {0, 0, 0, 0};
+        for (int g = tid; g < (int)gridDim.x; g += kProbeWG)
+            for (int q = 0; q < 4; ++q) acc[q] += __hip_atomic_load(&slots[g * 4 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+        __syncthreads();
+        if (__lane_id() == 0)
+            for (int q = 0; q < 4; ++q) red[q][wave] = acc[q];
+        __syncthreads();
+    }
+    if (last && tid == 0) {
+        unsigned long long tot[4] = {0, 0, 0, 0};
+        for (int w = 0; w < kProbeWG / kWave; ++w)
+            for (int q = 0; q < 4; ++q) tot[q] += red[q][w];
+        const unsigned long long desc = tot[0];
+        const unsigned long long asc = tot[1];
+        const unsigned long long sdesc = tot[2];
+        const unsigned long long spairs = tot[3];
         const bool mixed = ld_agent(&ctl->mixed) != 0;
         int path;
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
@@ -167,24 +310,6 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         ctl->n_kept = 0;
         ctl->bad_join = 0;
         ctl->ticket2 = 0;
-    }
-}
-
-// In-place reversal of keys (and payloads): swaps i and n-1-i.
-template <class S>
-__global__ __launch_bounds__(kRevWG) void k_reverse(S* keys, uint32_t* pay, int64_t n, const Ctl* ctl) {
-    if (!path_is(ctl, SR_PATH_REVERSED)) return;
-    const int64_t half = n / 2;
-    for (int64_t i = (int64_t)blockIdx.x * kRevWG + threadIdx.x; i < half; i += (int64_t)gridDim.x * kRevWG) {
-        const int64_t j = n - 1 - i;
-        const S a = keys[i], b = keys[j];
-        keys[i] = b;
-        keys[j] = a;
-        if (pay) {
-            const uint32_t pa = pay[i], pb = pay[j];
-            pay[i] = pb;
-            pay[j] = pa;
-        }
     }
 }
 
@@ -288,6 +413,7 @@ sr_status hip_fail(hipError_t e, const char* what) {
 std::mutex g_mu;
 int g_force_path = -1;
 bool g_profile = false;
+int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
 
 struct ProfRec {
     std::string name;
@@ -347,8 +473,11 @@ struct LastCall {
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 std::map<hipStream_t, LastCall> g_last;
 
+// Workspace header: control block, then the probe's per-workgroup slots.
 constexpr size_t kCtlBytes = 256;
+constexpr size_t kHdrBytes = 64 * 1024;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
+static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 <= kHdrBytes, "probe slots");
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -364,7 +493,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
         if (!slot) slot = new Workspace();
         ws = slot;
     }
-    const size_t need = kCtlBytes + round_up(data_bytes, 256);
+    const size_t need = kHdrBytes + round_up(data_bytes, 256);
     if (ws->bytes < need) {
         if (ws->base) {
             e = hipStreamSynchronize(st);
@@ -399,7 +528,30 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
     return SR_OK;
 }
 
-void* ws_data(Workspace* ws) { return (char*)ws->base + kCtlBytes; }
+void* ws_data(Workspace* ws) { return (char*)ws->base + kHdrBytes; }
+unsigned long long* ws_slots(Workspace* ws) {
+    return reinterpret_cast<unsigned long long*>((char*)ws->base + kCtlBytes);
+}
+
+// Resident workgroups of a kernel on the whole device (persistent grids).
+template <class K>
+int64_t resident_blocks(K kernel, int threads) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int64_t> cache;
+    int dev = 0;
+    hipGetDevice(&dev);
+    const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t r = (int64_t)std::max(cus, 1) * per_cu;
+    cache[key] = r;
+    return r;
+}
 
 int ceil_log2(int64_t x) {
     int r = 0;
@@ -433,32 +585,41 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
         // One tile: sort in place, no probe.
         ProfScope ps(st, "tile_sort");
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, st, keys, keys,
-                           pay, pay, n, (const Ctl*)nullptr, 0);
+                           pay, pay, n, (const Ctl*)nullptr, 0, keys, pay);
         SR_LAUNCH_CHECK("tile_sort");
         lc.trivial = 1;
         std::lock_guard<std::mutex> lk(g_mu);
         g_last[st] = lc;
         return SR_OK;
     }
-    Workspace* ws = nullptr;
+    const int64_t nchunks = cdiv(n, CH);
+    const size_t co_bytes = round_up((size_t)(nchunks + 2) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
-    sr_status s = get_workspace(st, kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws);
+    Workspace* ws = nullptr;
+    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws);
     if (s != SR_OK) return s;
     Ctl* ctl = ws->ctl;
-    S* skeys = static_cast<S*>(ws_data(ws));
-    uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>((char*)ws_data(ws) + kbytes) : nullptr;
+    char* wd = static_cast<char*>(ws_data(ws));
+    int64_t* co = reinterpret_cast<int64_t*>(wd);
+    S* skeys = reinterpret_cast<S*>(wd + co_bytes);
+    uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes) : nullptr;
+    const bool use_partition = n >= g_partition_min_n;
 
     {
         ProfScope ps(st, "probe");
-        hipLaunchKernelGGL(k_probe<C>, dim3((unsigned)cdiv(n - 1, kProbeTile)), dim3(kProbeWG), 0, st,
-                           (const S*)keys, n, ctl, 0);
+        const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
+        hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, st, (const S*)keys, n, ctl, ws_slots(ws), 0);
         SR_LAUNCH_CHECK("probe");
     }
+    S* kbuf[2] = {keys, skeys};
+    uint32_t* pbuf[2] = {pay, spay};
     {
-        ProfScope ps(st, "reverse");
-        const unsigned g = (unsigned)std::min<int64_t>(cdiv(n / 2, kRevWG * 4), 8192);
-        hipLaunchKernelGGL(k_reverse<S>, dim3(std::max(1u, g)), dim3(kRevWG), 0, st, keys, pay, n, (const Ctl*)ctl);
-        SR_LAUNCH_CHECK("reverse");
+        // GENERAL: tile sort; REVERSED: in-place reversal (same launch)
+        ProfScope ps(st, "tile_sort");
+        const int to = M % 2;
+        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
+                           keys, kbuf[to], pay, pbuf[to], n, (const Ctl*)ctl, (int)SR_PATH_GENERAL, keys, pay);
+        SR_LAUNCH_CHECK("tile_sort");
     }
     if (PAIRS) {
         ProfScope ps(st, "regroup");
@@ -467,22 +628,28 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
                            (const Ctl*)ctl);
         SR_LAUNCH_CHECK("regroup");
     }
-    S* kbuf[2] = {keys, skeys};
-    uint32_t* pbuf[2] = {pay, spay};
-    {
-        ProfScope ps(st, "tile_sort");
-        const int to = M % 2;
-        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
-                           keys, kbuf[to], pay, pbuf[to], n, (const Ctl*)ctl, (int)SR_PATH_GENERAL);
-        SR_LAUNCH_CHECK("tile_sort");
-    }
     for (int k = 0; k < M; ++k) {
-        ProfScope ps(st, "merge");
         const int from = (M - k) % 2, to = (M - k - 1) % 2;
         const int64_t width = (int64_t)T << k;
-        hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)cdiv(n, CH)), dim3(TN::MWG), 0, st,
-                           (const S*)kbuf[from], kbuf[to], (const uint32_t*)pbuf[from], pbuf[to], n, width,
-                           (const Ctl*)ctl, (int)SR_PATH_GENERAL);
+        if (use_partition) {
+            ProfScope ps(st, "partition");
+            hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, st,
+                               (const S*)kbuf[from], n, width, CH, nchunks, co, (const Ctl*)ctl,
+                               (int)SR_PATH_GENERAL);
+            SR_LAUNCH_CHECK("partition");
+        }
+        ProfScope ps(st, "merge");
+        if (use_partition) {
+            auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
+            const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, st, (const S*)kbuf[from], kbuf[to],
+                               (const uint32_t*)pbuf[from], pbuf[to], n, width, (const Ctl*)ctl,
+                               (int)SR_PATH_GENERAL, (const int64_t*)co, nchunks);
+        } else {
+            hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0, st,
+                               (const S*)kbuf[from], kbuf[to], (const uint32_t*)pbuf[from], pbuf[to], n, width,
+                               (const Ctl*)ctl, (int)SR_PATH_GENERAL, (const int64_t*)nullptr);
+        }
         SR_LAUNCH_CHECK("merge");
     }
     lc.trivial = 0;
@@ -589,7 +756,7 @@ sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nse
     g_err.clear();
     const int es = elem_bytes(dt);
     if (es == 0 || !bytes) return fail(SR_ERR_INVALID_ARGUMENT, "bad argument");
-    size_t b = kCtlBytes + round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
+    size_t b = kHdrBytes + round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
     b += round_up((nseg + 1) * 8 * 4, 256);
     *bytes = std::max(b, (size_t)1 << 20);
     return SR_OK;
@@ -653,6 +820,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
         g_force_path = (int)value;
         return SR_OK;
     }
+    if (std::strcmp(name, "partition_min_n") == 0) {
+        if (value < 0) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= 0");
+        g_partition_min_n = value;
+        return SR_OK;
+    }
     if (std::strcmp(name, "profile") == 0) {
         if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "profile is 0 or 1");
         g_profile = value != 0;
@@ -664,29 +836,32 @@ sr_status sr_set_option(const char* name, int64_t value) {
 sr_status sr_profile_collect(const char* prefix, int64_t* launches, double* total_ms) {
     g_err.clear();
     if (!launches || !total_ms) return fail(SR_ERR_INVALID_ARGUMENT, "NULL output");
-    std::vector<ProfRec> recs;
+    const size_t pl = prefix ? std::strlen(prefix) : 0;
+    std::vector<ProfRec> mine;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        recs.swap(g_prof);
+        std::vector<ProfRec> keep;
+        for (auto& r : g_prof) {
+            if (pl == 0 || r.name.compare(0, pl, prefix) == 0) mine.push_back(r);
+            else keep.push_back(r);
+        }
+        g_prof.swap(keep);
     }
-    const size_t pl = prefix ? std::strlen(prefix) : 0;
     int64_t cnt = 0;
     double ms = 0;
     sr_status st = SR_OK;
-    for (auto& r : recs) {
+    for (auto& r : mine) {
         hipError_t e = hipEventSynchronize(r.b);
         if (e != hipSuccess && st == SR_OK) st = hip_fail(e, "hipEventSynchronize");
-        if (pl == 0 || r.name.compare(0, pl, prefix) == 0) {
-            float t = 0;
-            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
-                ms += t;
-                cnt++;
-            }
+        float t = 0;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            ms += t;
+            cnt++;
         }
     }
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        for (auto& r : recs) {
+        for (auto& r : mine) {
             g_event_pool.push_back(r.a);
             g_event_pool.push_back(r.b);
         }

@@ -188,91 +188,155 @@ struct TileSort {
 // ================================================================== merge
 // One output chunk of WG*IT keys of one merge pass: the runs A = [gs, gs+w)
 // and B = [gs+w, gs+2w) of src (clipped to n) are merged into dst[gs, ...).
-// The chunk's input windows come from two Merge Path searches (wavefronts 0
-// and 1), are staged in LDS, and every thread merges IT outputs serially
-// after its own co-rank search inside LDS.  Ties take A: stable.
+// Phases: window bounds (two Merge Path co-ranks, precomputed or searched by
+// wavefronts 0 and 1), window loads into registers, staging in LDS, a
+// per-thread co-rank search inside LDS and a serial merge of IT outputs,
+// then the outputs go back through LDS (padded by one slot per 16, so the
+// blocked writes do not collide in banks) and out as coalesced vectors.
+// Ties take A: stable.
 template <class C, int WG, int IT, bool PAIRS>
 struct MergeChunk {
     using S = typename C::S;
     using U = typename C::U;
     static constexpr int CH = WG * IT;
     static constexpr int VN = 16 / sizeof(S);
+    static constexpr int PADDED = CH + CH / 16;
     static_assert(WG >= 2 * kWave, "two wavefronts search the window bounds");
+    static_assert(IT % VN == 0, "whole vectors per thread");
 
+    struct Buf {
+        U k[PADDED];
+        uint32_t pay[PAIRS ? PADDED : 1];
+    };
     struct Smem {
-        U k[CH];
-        uint32_t pay[PAIRS ? CH : 1];
+        Buf b;
         int64_t co[2];
     };
 
-    // src/dst/psrc/pdst point at the start of the (segment) array of length n.
-    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
-                               int64_t n, int64_t width, int64_t out0) {
-        const int tid = threadIdx.x;
-        const int64_t gs = out0 / (2 * width) * (2 * width);
-        const int64_t la = (n - gs) < width ? (n - gs) : width;
+    static __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
+
+    // Window of one chunk: where its inputs are and its loaded elements.
+    struct Win {
+        int64_t out0;   // first output of the chunk (segment-relative)
+        int64_t gA;     // first A element of the window (segment-relative)
+        int64_t gB;     // first B element of the window
+        int na, cnt;
+        S x[IT];
+        uint32_t px[PAIRS ? IT : 1];
+    };
+
+    static __device__ __forceinline__ void bounds(const S* src, int64_t n, int64_t width, int64_t out0,
+                                                  int64_t& gs, int64_t& la, int64_t& lb, int64_t& d0, int64_t& d1) {
+        gs = out0 / (2 * width) * (2 * width);
+        la = (n - gs) < width ? (n - gs) : width;
         const int64_t rest = n - gs - la;
-        const int64_t lb = rest < width ? rest : width;
-        const int64_t d0 = out0 - gs;
-        const int64_t d1 = (d0 + CH) < (la + lb) ? (d0 + CH) : (la + lb);
-        const S* A = src + gs;
-        const S* B = A + la;
-        const int wave = tid / kWave;
+        lb = rest < width ? rest : width;
+        d0 = out0 - gs;
+        d1 = (d0 + CH) < (la + lb) ? (d0 + CH) : (la + lb);
+    }
+
+    // Window of the chunk starting at out0 from precomputed co-ranks (co is
+    // indexed by chunk number relative to the same array start).
+    static __device__ __forceinline__ void window_from_co(const S* src, int64_t n, int64_t width, int64_t out0,
+                                                          const int64_t* co, Win& w) {
+        int64_t gs, la, lb, d0, d1;
+        bounds(src, n, width, out0, gs, la, lb, d0, d1);
+        const int64_t c = out0 / CH;
+        const int64_t i0 = co[c];
+        const int64_t i1 = d1 == la + lb ? la : co[c + 1];
+        w.out0 = out0;
+        w.gA = gs + i0;
+        w.gB = gs + la + (d0 - i0);
+        w.na = (int)(i1 - i0);
+        w.cnt = (int)(d1 - d0);
+    }
+
+    // Same, with the co-ranks searched here by wavefronts 0 and 1.
+    static __device__ __forceinline__ void window_search(Smem& sm, const S* src, int64_t n, int64_t width,
+                                                         int64_t out0, Win& w) {
+        int64_t gs, la, lb, d0, d1;
+        bounds(src, n, width, out0, gs, la, lb, d0, d1);
+        const int wave = threadIdx.x / kWave;
         if (wave < 2) {
-            const int64_t c = corank_wave<C>(A, la, B, lb, wave == 0 ? d0 : d1);
+            const int64_t c = corank_wave<C>(src + gs, la, src + gs + la, lb, wave == 0 ? d0 : d1);
             if (__lane_id() == 0) sm.co[wave] = c;
         }
         __syncthreads();
         const int64_t i0 = sm.co[0], i1 = sm.co[1];
-        const int64_t j0 = d0 - i0, j1 = d1 - i1;
-        const int na = (int)(i1 - i0), nb = (int)(j1 - j0);
-        const int cnt = na + nb;
-        for (int e = tid; e < cnt; e += WG) {
-            const bool fa = e < na;
-            const int64_t gi = fa ? gs + i0 + e : gs + la + j0 + (e - na);
-            sm.k[e] = C::enc(src[gi]);
-            if constexpr (PAIRS) sm.pay[e] = psrc[gi];
-        }
-        __syncthreads();
+        w.out0 = out0;
+        w.gA = gs + i0;
+        w.gB = gs + la + (d0 - i0);
+        w.na = (int)(i1 - i0);
+        w.cnt = (int)(d1 - d0);
+    }
 
-        const int t0 = tid * IT;
-        U v[IT];
-        uint32_t pv[IT];
-        if (t0 < cnt) {
-            const U* Aw = sm.k;
-            const U* Bw = sm.k + na;
-            int i = corank_lds(Aw, na, Bw, nb, t0);
-            int j = t0 - i;
-            const int last = cnt - 1;
-            int ia = i < na ? i : last;
-            int ib = na + (j < nb ? j : nb - 1);
-            ib = ib < 0 ? 0 : ib;
-            U a = sm.k[ia], b = sm.k[ib];
+    // Issue every window load of this thread (they stay in flight until stage()).
+    static __device__ __forceinline__ void load(const S* src, const uint32_t* psrc, Win& w) {
+        const int tid = threadIdx.x;
 #pragma unroll
-            for (int r = 0; r < IT; ++r) {
-                const bool ta = (j >= nb) || (i < na && a <= b);
-                v[r] = ta ? a : b;
-                if constexpr (PAIRS) pv[r] = sm.pay[ta ? (i < na ? i : last) : (na + j < cnt ? na + j : last)];
-                i += ta ? 1 : 0;
-                j += ta ? 0 : 1;
-                int nx = ta ? i : na + j;
-                nx = nx < last ? nx : last;
-                const U kn = sm.k[nx];
-                a = ta ? kn : a;
-                b = ta ? b : kn;
+        for (int r = 0; r < IT; ++r) {
+            const int e = tid + r * WG;
+            if (e < w.cnt) {
+                const int64_t gi = e < w.na ? w.gA + e : w.gB + (e - w.na);
+                w.x[r] = src[gi];
+                if constexpr (PAIRS) w.px[r] = psrc[gi];
             }
         }
-        __syncthreads();
-        if (t0 < cnt) {
+    }
+
+    static __device__ __forceinline__ void stage(Buf& b, const Win& w) {
+        const int tid = threadIdx.x;
 #pragma unroll
-            for (int r = 0; r < IT; ++r) {
-                if (t0 + r < cnt) {
-                    sm.k[t0 + r] = v[r];
-                    if constexpr (PAIRS) sm.pay[t0 + r] = pv[r];
-                }
+        for (int r = 0; r < IT; ++r) {
+            const int e = tid + r * WG;
+            if (e < w.cnt) {
+                b.k[e] = C::enc(w.x[r]);
+                if constexpr (PAIRS) b.pay[e] = w.px[r];
             }
         }
-        __syncthreads();
+    }
+
+    // Serial merge of this thread's IT outputs from the staged window.
+    static __device__ __forceinline__ void merge(const Buf& b, int na, int cnt, U (&v)[IT], uint32_t (&pv)[IT]) {
+        const int t0 = threadIdx.x * IT;
+        if (t0 >= cnt) return;
+        const int nb = cnt - na;
+        int i = corank_lds(b.k, na, b.k + na, nb, t0);
+        int j = t0 - i;
+        const int last = cnt - 1;
+        int ia = i < na ? i : last;
+        int ib = na + (j < nb ? j : nb - 1);
+        ib = ib < 0 ? 0 : ib;
+        U a = b.k[ia], bb = b.k[ib];
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const bool ta = (j >= nb) || (i < na && a <= bb);
+            v[r] = ta ? a : bb;
+            if constexpr (PAIRS) pv[r] = b.pay[ta ? (i < na ? i : last) : (na + j < cnt ? na + j : last)];
+            i += ta ? 1 : 0;
+            j += ta ? 0 : 1;
+            int nx = ta ? i : na + j;
+            nx = nx < last ? nx : last;
+            const U kn = b.k[nx];
+            a = ta ? kn : a;
+            bb = ta ? bb : kn;
+        }
+    }
+
+    static __device__ __forceinline__ void stage_out(Buf& b, int cnt, const U (&v)[IT], const uint32_t (&pv)[IT]) {
+        const int t0 = threadIdx.x * IT;
+        if (t0 >= cnt) return;
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            if (t0 + r < cnt) {
+                b.k[pad(t0 + r)] = v[r];
+                if constexpr (PAIRS) b.pay[pad(t0 + r)] = pv[r];
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void store(const Buf& b, S* dst, uint32_t* pdst, int64_t out0, int cnt) {
+        const int tid = threadIdx.x;
         S* out = dst + out0;
         if (cnt == CH && aligned16(out)) {
 #pragma unroll
@@ -280,15 +344,93 @@ struct MergeChunk {
                 const int e0 = (tid + q * WG) * VN;
                 V16<S> x;
 #pragma unroll
-                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[e0 + j]);
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(b.k[pad(e0 + j)]);
                 reinterpret_cast<V16<S>*>(out)[tid + q * WG] = x;
             }
         } else {
-            for (int e = tid; e < cnt; e += WG) out[e] = C::dec(sm.k[e]);
+            for (int e = tid; e < cnt; e += WG) out[e] = C::dec(b.k[pad(e)]);
         }
         if constexpr (PAIRS) {
             uint32_t* pout = pdst + out0;
-            for (int e = tid; e < cnt; e += WG) pout[e] = sm.pay[e];
+            if (cnt == CH && aligned16(pout)) {
+#pragma unroll
+                for (int q = 0; q < IT / 4; ++q) {
+                    const int e0 = (tid + q * WG) * 4;
+                    uint4 x;
+                    x.x = b.pay[pad(e0)];
+                    x.y = b.pay[pad(e0 + 1)];
+                    x.z = b.pay[pad(e0 + 2)];
+                    x.w = b.pay[pad(e0 + 3)];
+                    reinterpret_cast<uint4*>(pout)[tid + q * WG] = x;
+                }
+            } else {
+                for (int e = tid; e < cnt; e += WG) pout[e] = b.pay[pad(e)];
+            }
+        }
+    }
+
+    // One chunk, start to end.  src/dst/psrc/pdst point at the start of the
+    // (segment) array of length n; co (optional) holds precomputed co-ranks.
+    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
+                               int64_t n, int64_t width, int64_t out0, const int64_t* co = nullptr) {
+        Win w;
+        if (co != nullptr) window_from_co(src, n, width, out0, co, w);
+        else window_search(sm, src, n, width, out0, w);
+        load(src, psrc, w);
+        stage(sm.b, w);
+        __syncthreads();
+        U v[IT];
+        uint32_t pv[IT];
+        merge(sm.b, w.na, w.cnt, v, pv);
+        __syncthreads();
+        stage_out(sm.b, w.cnt, v, pv);
+        __syncthreads();
+        store(sm.b, dst, pdst, out0, w.cnt);
+    }
+};
+
+// Persistent, double-buffered form of one merge pass: a workgroup walks the
+// chunks c = blockIdx.x, + gridDim.x, ...; while it merges chunk c out of one
+// LDS buffer, the window loads of its next chunk are already in flight into
+// registers, and they are staged into the other buffer.
+template <class C, int WG, int IT, bool PAIRS>
+struct MergePersistent {
+    using MC = MergeChunk<C, WG, IT, PAIRS>;
+    using S = typename C::S;
+    using U = typename C::U;
+    static constexpr int CH = MC::CH;
+    struct Smem {
+        typename MC::Buf b[2];
+    };
+
+    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
+                               int64_t n, int64_t width, const int64_t* co, int64_t nchunks) {
+        int64_t c = blockIdx.x;
+        if (c >= nchunks) return;
+        typename MC::Win w;
+        MC::window_from_co(src, n, width, c * CH, co, w);
+        MC::load(src, psrc, w);
+        int buf = 0;
+        for (;;) {
+            MC::stage(sm.b[buf], w);
+            const int na = w.na, cnt = w.cnt;
+            const int64_t out0 = w.out0;
+            __syncthreads();
+            const int64_t cn = c + gridDim.x;
+            if (cn < nchunks) {
+                MC::window_from_co(src, n, width, cn * CH, co, w);
+                MC::load(src, psrc, w);
+            }
+            U v[IT];
+            uint32_t pv[IT];
+            MC::merge(sm.b[buf], na, cnt, v, pv);
+            __syncthreads();
+            MC::stage_out(sm.b[buf], cnt, v, pv);
+            __syncthreads();
+            MC::store(sm.b[buf], dst, pdst, out0, cnt);
+            if (cn >= nchunks) break;
+            c = cn;
+            buf ^= 1;
         }
     }
 };

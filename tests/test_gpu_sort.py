@@ -166,3 +166,18 @@ def test_two_million_four_types(gpu, kind):
     a = inputs.int32_of_type(kind, n, inputs.seed_for(2, inputs.TYPES.index(kind), n))
     got = gpu_sort_keys(gpu, a, "int32")
     assert np.array_equal(got, oracle.sort_keys(a)), kind
+
+
+@pytest.mark.parametrize("n", [8193, 40_000, 262_147, 1_000_003])
+def test_separate_partition_launch(gpu, n):
+    """Merge passes with the Merge Path partition in its own launch."""
+    gpu.set_option("partition_min_n", 0)
+    try:
+        a = inputs.random_int32(n, seed=n)
+        assert np.array_equal(gpu_sort_keys(gpu, a, "int32"), oracle.sort_keys(a))
+        k, p = inputs.runs_uint64(n, seed=n, tie_stress=True)
+        gk, gp = gpu_sort_pairs(gpu, k, p, "uint64")
+        wk, wp = oracle.sort_pairs(k, p)
+        assert np.array_equal(gk, wk) and np.array_equal(gp, wp)
+    finally:
+        gpu.set_option("partition_min_n", 1 << 22)
