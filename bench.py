@@ -73,7 +73,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10, help="timed reps per type at 256M")
     ap.add_argument("--no-big", action="store_true", help="skip the n=256M section")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["small", "big-random"], default=None,
+    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few"],
+                    default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
 
@@ -157,8 +158,8 @@ def main():
     roofline = None
     per_big = {}
     copy_gbps = None
-    if not args.no_big and args.only in (None, "big-random"):
-        big_types = types if args.only is None else ["random"]
+    if not args.no_big and (args.only is None or args.only.startswith("big-")):
+        big_types = types if args.only is None else [args.only[4:]]
         work = torch.empty(N_BIG, dtype=torch.int32, device=dev)
         # bandwidth reference: 16-byte copy of 1 GiB
         src = torch.empty(N_BIG, dtype=torch.int32, device=dev)

@@ -64,11 +64,13 @@ typedef enum {
 
 typedef struct {
     int32_t path;          /* sr_path */
-    int32_t passes;        /* full read+write passes over n keys (fractional parts rounded up) */
+    int32_t passes;        /* read+write passes over the n keys, rounded up; a pass
+                              over m < n keys counts m/n (the probe's reads are
+                              not counted) */
     int64_t n;             /* keys sorted by the call */
     int64_t descents;      /* probe: descents seen (exact when path is SORTED/REVERSED) */
     int64_t outliers;      /* OUTLIER path: keys moved to the outlier list */
-    double bytes_moved;    /* algorithmic HBM bytes: passes x 2 x n x element bytes */
+    double bytes_moved;    /* algorithmic HBM bytes: unrounded passes x 2 x n x element bytes */
 } sr_stats;
 
 /*
@@ -127,6 +129,8 @@ const char *sr_last_error_message(void);
  *                 (SR_PATH_GENERAL is always safe).
  *   "profile"     1 = record a HIP event pair around every kernel the sort
  *                 path launches (on the caller's stream); 0 = off (default).
+ *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
+ *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
  *   "partition_min_n"  from this n on, every merge pass is preceded by a
  *                 separate Merge Path partition launch; below it each merge
  *                 workgroup searches its own window bounds (default 2^22).

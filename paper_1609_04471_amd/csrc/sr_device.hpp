@@ -55,24 +55,23 @@ template <class U>
 __device__ __forceinline__ U key_max() { return (U)~(U)0; }
 
 // --------------------------------------------------- device control block
-// One per workspace.  The probe's last workgroup turns the counters into the
-// plan and zeroes them again, so every call finds them cleared.
+// One per workspace.  The probe's last workgroup writes the plan and clears
+// the per-call counters, so every call finds them cleared.
 struct Ctl {
-    unsigned long long desc;          // descents seen by the probe
-    unsigned long long asc;           // ascents seen by the probe
-    unsigned long long sample_desc;   // descents among sampled neighbour pairs
-    unsigned long long sample_pairs;  // sampled neighbour pairs
-    unsigned int mixed;               // some workgroup saw both an ascent and a descent
-    unsigned int ticket;              // workgroups of the probe that finished
+    unsigned long long unused0[4];
+    unsigned int mixed;               // some probe workgroup saw both an ascent and a descent
+    unsigned int ticket;              // probe workgroups that finished
     int path;                         // sr_path chosen by the plan
     int force_path;                   // -1 or a forced sr_path
-    unsigned long long n_out;         // OUTLIER path: outlier count
-    unsigned long long n_kept;        // OUTLIER path: kept count
-    unsigned int bad_join;            // OUTLIER path: kept list not sorted across tiles
-    unsigned int ticket2;
-    int out_passes;                   // OUTLIER path: merge passes needed for the outliers
+    unsigned long long m;             // OUTLIER: number of outliers
+    unsigned long long n_kept;        // OUTLIER: number of kept keys (written by the last tile)
+    unsigned int bad_join;            // OUTLIER: kept keys not sorted somewhere: fall back
+    unsigned int ticket2;             // OUTLIER: tile ids handed out by classify
+    unsigned int ticket3;             // OUTLIER: classify workgroups finished
+    unsigned int epoch;               // call counter stamped into the look-back status words
+    int job_passes;                   // OUTLIER: merge passes of the outlier sort
     int pad0;
-    unsigned long long reserved[6];
+    unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
 };
 
 // Plain relaxed agent-scope accessors (coherent across the XCDs' L2s).

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -56,6 +57,7 @@ constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
 constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
 constexpr int kRevWG = 256;
 constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over its tiles)
+constexpr unsigned int kProbeGroup = 32;  // probe workgroups per first-level ticket counter
 
 __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
     return ctl == nullptr || ld_agent(&ctl->path) == want;
@@ -63,95 +65,498 @@ __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
 
 // ============================================================== kernels
 
-// Tile sort of the GENERAL path.  The same launch carries the REVERSED path:
-// then workgroup b swaps the pairs (i, n-1-i) for i in its half-tile share
-// [b*T/2, (b+1)*T/2) of [0, n/2), in place in `keys`.
+// Tile-sort launch.  GENERAL / OUTLIER: the tile sort of the job's array
+// (resolve_tile).  REVERSED: the same launch reverses the array instead --
+// workgroup b swaps the pairs (i, n-1-i) for i in its half-tile share
+// [b*T/2, (b+1)*T/2) of [0, n/2), in place in U.
 template <class C, int WG, int IT, bool PAIRS>
-__global__ __launch_bounds__(WG) void k_tile_sort(const typename C::S* src, typename C::S* dst,
-                                                  const uint32_t* psrc, uint32_t* pdst, int64_t n,
-                                                  const Ctl* ctl, int need, typename C::S* keys,
-                                                  uint32_t* pay) {
+__global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::S* S1, uint32_t* PU,
+                                                  uint32_t* PS1, int64_t n, int M, const Ctl* ctl) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
-    if (ctl != nullptr) {
-        const int path = ld_agent(&ctl->path);
-        if (path == SR_PATH_REVERSED) {
-            constexpr int H = TS::T / 2;
-            constexpr int R = H / WG;
-            const int64_t half = n / 2;
-            const int64_t i0 = (int64_t)blockIdx.x * H + threadIdx.x;
-            S a[R], b[R];
-            uint32_t pa[R], pb[R];
+    if (ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_REVERSED) {
+        constexpr int H = TS::T / 2;
+        constexpr int R = H / WG;
+        const int64_t half = n / 2;
+        const int64_t i0 = (int64_t)blockIdx.x * H + threadIdx.x;
+        S a[R], b[R];
+        uint32_t pa[R], pb[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t i = i0 + (int64_t)r * WG;
-                if (i < half) {
-                    a[r] = keys[i];
-                    b[r] = keys[n - 1 - i];
-                    if constexpr (PAIRS) {
-                        pa[r] = pay[i];
-                        pb[r] = pay[n - 1 - i];
-                    }
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = i0 + (int64_t)r * WG;
+            if (i < half) {
+                a[r] = U[i];
+                b[r] = U[n - 1 - i];
+                if constexpr (PAIRS) {
+                    pa[r] = PU[i];
+                    pb[r] = PU[n - 1 - i];
                 }
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t i = i0 + (int64_t)r * WG;
-                if (i < half) {
-                    keys[i] = b[r];
-                    keys[n - 1 - i] = a[r];
-                    if constexpr (PAIRS) {
-                        pay[i] = pb[r];
-                        pay[n - 1 - i] = pa[r];
-                    }
-                }
-            }
-            return;
         }
-        if (path != need) return;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = i0 + (int64_t)r * WG;
+            if (i < half) {
+                U[i] = b[r];
+                U[n - 1 - i] = a[r];
+                if constexpr (PAIRS) {
+                    PU[i] = pb[r];
+                    PU[n - 1 - i] = pa[r];
+                }
+            }
+        }
+        return;
     }
-    __shared__ typename TS::Smem sm;
+    const PassView<S> v = resolve_tile(ctl, U, S1, PU, PS1, n, M);
+    if (!v.active) return;
     const int64_t base = (int64_t)blockIdx.x * TS::T;
-    const int valid = (int)((n - base) < TS::T ? (n - base) : TS::T);
-    TS::run(sm, src + base, dst + base, PAIRS ? psrc + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
+    if (base >= v.n) return;
+    __shared__ typename TS::Smem sm;
+    const int valid = (int)((v.n - base) < TS::T ? (v.n - base) : TS::T);
+    TS::run(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
+            valid);
 }
 
-// Merge Path partition of one merge pass: co[c] = co-rank of the start of
+// Merge Path partition of merge slot k: co[c] = co-rank of the start of
 // output chunk c (c*CH) inside its pair of runs.  One thread per chunk.
 template <class C>
-__global__ __launch_bounds__(256) void k_partition(const typename C::S* src, int64_t n, int64_t width,
-                                                   int CH, int64_t nchunks, int64_t* co, const Ctl* ctl,
-                                                   int need) {
-    if (!path_is(ctl, need)) return;
+__global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C::S* S1, int64_t n, int M,
+                                                   int64_t T, int k, int CH, int64_t* co, const Ctl* ctl) {
+    using S = typename C::S;
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k);
+    if (!v.active) return;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= nchunks) return;
+    if (c * CH >= v.n) return;
     const int64_t out0 = c * CH;
-    const int64_t gs = out0 / (2 * width) * (2 * width);
-    const int64_t la = (n - gs) < width ? (n - gs) : width;
-    const int64_t rest = n - gs - la;
-    const int64_t lb = rest < width ? rest : width;
-    co[c] = corank_thread<C>(src + gs, la, src + gs + la, lb, out0 - gs);
+    int64_t gs, la, lb;
+    if (v.split >= 0) {
+        gs = 0;
+        la = v.split;
+        lb = v.n - v.split;
+    } else {
+        gs = out0 / (2 * v.width) * (2 * v.width);
+        la = (v.n - gs) < v.width ? (v.n - gs) : v.width;
+        const int64_t rest = v.n - gs - la;
+        lb = rest < v.width ? rest : v.width;
+    }
+    co[c] = corank_thread<C>(v.src + gs, la, v.src + gs + la, lb, out0 - gs);
 }
 
+// Merge slot k, one chunk per workgroup, co-ranks searched in the workgroup.
 template <class C, int WG, int IT, bool PAIRS>
-__global__ __launch_bounds__(WG) void k_merge(const typename C::S* src, typename C::S* dst,
-                                              const uint32_t* psrc, uint32_t* pdst, int64_t n,
-                                              int64_t width, const Ctl* ctl, int need, const int64_t* co) {
+__global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
+                                              int64_t n, int M, int64_t T, int k, const Ctl* ctl) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
-    if (!path_is(ctl, need)) return;
+    using S = typename C::S;
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
+    if (!v.active) return;
+    const int64_t out0 = (int64_t)blockIdx.x * MC::CH;
+    if (out0 >= v.n) return;
     __shared__ typename MC::Smem sm;
-    MC::run(sm, src, dst, psrc, pdst, n, width, (int64_t)blockIdx.x * MC::CH, co);
+    MC::run(sm, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, out0, nullptr);
 }
 
+// Merge slot k, persistent double-buffered, co-ranks from k_partition.
 template <class C, int WG, int IT, bool PAIRS>
-__global__ __launch_bounds__(WG) void k_merge_persist(const typename C::S* src, typename C::S* dst,
-                                                      const uint32_t* psrc, uint32_t* pdst, int64_t n,
-                                                      int64_t width, const Ctl* ctl, int need, const int64_t* co,
-                                                      int64_t nchunks) {
+__global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
+                                                      uint32_t* PS1, int64_t n, int M, int64_t T, int k,
+                                                      const int64_t* co, const Ctl* ctl) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
-    if (!path_is(ctl, need)) return;
+    using S = typename C::S;
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
+    if (!v.active) return;
     __shared__ typename MP::Smem sm;
-    MP::run(sm, src, dst, psrc, pdst, n, width, co, nchunks);
+    MP::run(sm, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
+}
+
+// --------------------------------------------------------------- outliers
+// Nearly-sorted input (the k-exchange class of Sec. 2, tied to the Rem
+// measure: the fewest keys whose removal leaves a sorted sequence).  Three
+// launches after the probe chose OUTLIER:
+//   k_classify  tile t (kClsTC keys plus kClsH halo keys on each side) in LDS:
+//               repeatedly drop keys at descents among the keys still kept --
+//               the larger key of a descent when its removal restores the
+//               order, else the smaller, else both -- until no descent is
+//               left, so the tile's kept keys are sorted.  Writes a kept bit
+//               mask, the kept count and the first/last kept key per tile.
+//   k_verify    (one workgroup) the kept keys form one sorted sequence iff
+//               no tile's first kept key is below the last kept key of the
+//               nearest earlier tile that kept any; prefix of the counts;
+//               sets the job (OUTLIER with m outliers if the joins hold and
+//               m <= n/2, else GENERAL -- U is still untouched).
+//   k_scatter   kept keys to S1[0, n-m) in input order, outliers to
+//               S1[n-m, n) (from the end backwards).
+constexpr int kClsWG = 256;
+constexpr int kClsPer = 17;
+constexpr int kClsW = kClsWG * kClsPer;  // 4352-key window
+constexpr int kClsTC = 4096;             // core keys per tile
+constexpr int kClsH = (kClsW - kClsTC) / 2;
+constexpr int kClsMaxIter = 48;
+
+__device__ __forceinline__ int ceil_log2_dev(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
+}
+
+template <class C>
+__global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, int64_t n, Ctl* ctl,
+                                                     unsigned int* flags, unsigned long long* tfirst,
+                                                     unsigned long long* tlast, unsigned long long* tcount) {
+    using U = typename C::U;
+    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+    __shared__ U sk[kClsW];
+    __shared__ uint16_t dx[kClsW];  // dense list of kept keys: window index of the q-th kept key
+    __shared__ uint8_t kp[kClsW];
+    __shared__ int wtot[kClsWG / kWave];
+    __shared__ int s_flag[2];
+    __shared__ U s_first, s_last;
+    __shared__ int s_kc;
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    if (tid < 2) s_flag[tid] = 0;
+    __syncthreads();
+    const int64_t t = blockIdx.x;
+    const int64_t ntiles = (n + kClsTC - 1) / kClsTC;
+    const int64_t c0 = t * kClsTC;
+    const int64_t c1 = (c0 + kClsTC) < n ? (c0 + kClsTC) : n;
+    const int64_t w0 = c0 - kClsH > 0 ? c0 - kClsH : 0;
+    const int64_t w1 = (c1 + kClsH) < n ? (c1 + kClsH) : n;
+    const int wn = (int)(w1 - w0);
+    {
+        // all window loads in flight before the first LDS store
+        typename C::S xv[kClsPer];
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            const int j = tid + r * kClsWG;
+            if (j < wn) xv[r] = keys[w0 + j];
+        }
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            const int j = tid + r * kClsWG;
+            if (j < wn) sk[j] = C::enc(xv[r]);
+            kp[j] = j < wn ? 1 : 0;
+        }
+    }
+    __syncthreads();
+
+    bool converged = false;
+    const int bj = tid * kClsPer;
+    {
+        // Fast path: the first removal round on the raw window (every key is
+        // still kept, so no compaction is needed), then a check of each kept
+        // key against the next kept key.  Only a tile with a descent left
+        // goes through the compacting rounds below.
+        bool rem = false;
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            const int q = bj + r;
+            if (q + 1 < wn && sk[q] > sk[q + 1]) {
+                bool ra = q == 0 || sk[q - 1] <= sk[q + 1];
+                bool rb = !ra && (q + 2 >= wn || sk[q] <= sk[q + 2]);
+                if (!ra && !rb) ra = rb = true;
+                if (ra) kp[q] = 0;
+                if (rb) kp[q + 1] = 0;
+                rem = true;
+            }
+        }
+        if (rem) s_flag[0] = 1;
+        __syncthreads();
+        if (s_flag[0] == 0) {
+            converged = true;
+        } else {
+            bool desc = false;
+#pragma unroll
+            for (int r = 0; r < kClsPer; ++r) {
+                const int q = bj + r;
+                if (q < wn && kp[q]) {
+                    int j = q + 1;
+                    while (j < wn && !kp[j]) ++j;
+                    if (j < wn && sk[q] > sk[j]) desc = true;
+                }
+            }
+            if (desc) s_flag[1] = 1;
+            __syncthreads();
+            converged = s_flag[1] == 0;
+        }
+        __syncthreads();
+        if (tid < 2) s_flag[tid] = 0;
+        __syncthreads();
+    }
+    for (int iter = 0; !converged && iter < kClsMaxIter; ++iter) {
+        // dense list of the kept keys (block-wide exclusive scan of kp)
+        int pre[kClsPer];
+        int loc = 0;
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            pre[r] = loc;
+            loc += kp[bj + r];
+        }
+        int x = loc;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (lane == kWave - 1) wtot[wave] = x;
+        __syncthreads();
+        int off = x - loc, cnt = 0;
+#pragma unroll
+        for (int w = 0; w < kClsWG / kWave; ++w) {
+            cnt += wtot[w];
+            if (w < wave) off += wtot[w];
+        }
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            if (kp[bj + r]) dx[off + pre[r]] = (uint16_t)(bj + r);
+        }
+        __syncthreads();
+        bool rem = false;
+#pragma unroll
+        for (int r = 0; r < kClsPer; ++r) {
+            const int q = bj + r;
+            if (q + 1 < cnt && sk[dx[q]] > sk[dx[q + 1]]) {
+                bool ra = q == 0 || sk[dx[q - 1]] <= sk[dx[q + 1]];
+                bool rb = !ra && (q + 2 >= cnt || sk[dx[q]] <= sk[dx[q + 2]]);
+                if (!ra && !rb) ra = rb = true;
+                if (ra) kp[dx[q]] = 0;
+                if (rb) kp[dx[q + 1]] = 0;
+                rem = true;
+            }
+        }
+        if (rem) s_flag[iter & 1] = 1;
+        __syncthreads();
+        const bool any = s_flag[iter & 1] != 0;
+        if (tid == 0) s_flag[(iter + 1) & 1] = 0;
+        if (!any) {
+            converged = true;
+            break;
+        }
+    }
+
+    // the tile's core [c0, c1): kept ranks, first and last kept key
+    const int cs = (int)(c0 - w0), ce = (int)(c1 - w0);
+    constexpr int CP = kClsTC / kClsWG;
+    int kpre[CP];
+    int kl = 0;
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+        const int j = cs + tid * CP + r;
+        kpre[r] = kl;
+        kl += (j < ce && kp[j]) ? 1 : 0;
+    }
+    int x = kl;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) wtot[wave] = x;
+    __syncthreads();
+    int koff = x - kl, kc = 0;
+#pragma unroll
+    for (int w = 0; w < kClsWG / kWave; ++w) {
+        kc += wtot[w];
+        if (w < wave) koff += wtot[w];
+    }
+    if (kl > 0) {
+#pragma unroll
+        for (int r = 0; r < CP; ++r) {
+            const int j = cs + tid * CP + r;
+            if (j < ce && kp[j]) {
+                if (koff + kpre[r] == 0) s_first = sk[j];
+                if (koff + kpre[r] == kc - 1) s_last = sk[j];
+            }
+        }
+    }
+    __syncthreads();
+
+    // publish: kept flags of the core as a bit mask (bit i of word w = core key
+    // 32w + i), the kept count and the first/last kept key of the tile
+    {
+        const int li0 = tid * CP;  // this thread's 16 core keys: one half of a 32-bit word
+        unsigned int bits = 0;
+#pragma unroll
+        for (int r = 0; r < CP; ++r) {
+            const int j = cs + li0 + r;
+            if (j < ce && kp[j]) bits |= 1u << r;
+        }
+        const unsigned int other = (unsigned int)__shfl_xor((int)bits, 1);
+        if ((tid & 1) == 0) flags[t * (kClsTC / 32) + tid / 2] = bits | (other << CP);
+    }
+    if (tid == 0) {
+        if (!converged) atomicOr(&ctl->bad_join, 1u);
+        tcount[t] = (unsigned long long)kc;
+        tfirst[t] = kc > 0 ? (unsigned long long)s_first : 0ull;
+        tlast[t] = kc > 0 ? (unsigned long long)s_last : 0ull;
+    }
+}
+
+// Scatter of the outlier path: tile t's kept keys go to S1[kpref[t] + kept
+// rank inside the tile], its outliers to S1[n-1-(outliers before)], from the
+// kept bit masks of k_classify and the tile offsets of k_verify.  Keys are
+// assigned striped (key e of the tile to thread e mod 256), so loads and the
+// mostly consecutive kept stores coalesce; a key's kept rank is the popcount
+// prefix of the tile's mask words (scanned in LDS) plus the bits below it.
+template <class C>
+__global__ __launch_bounds__(kClsWG) void k_scatter(const typename C::S* keys, int64_t n, const Ctl* ctl,
+                                                    typename C::S* s1, const unsigned int* flags,
+                                                    const unsigned long long* kpref_t) {
+    using S = typename C::S;
+    constexpr int CP = kClsTC / kClsWG;
+    constexpr int NW = kClsTC / 32;  // mask words per tile
+    static_assert(NW <= kClsWG, "one word per thread in the scan");
+    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+    __shared__ unsigned int sw[NW];
+    __shared__ int spre[NW];
+    __shared__ int wtot[kClsWG / kWave];
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    const int64_t t = blockIdx.x;
+    const int64_t c0 = t * kClsTC;
+    const int64_t c1 = (c0 + kClsTC) < n ? (c0 + kClsTC) : n;
+    S x[CP];
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+        const int64_t g = c0 + r * kClsWG + tid;
+        if (g < c1) x[r] = keys[g];
+    }
+    const unsigned int w = tid < NW ? flags[t * NW + tid] : 0u;
+    if (tid < NW) sw[tid] = w;
+    const int pc = __builtin_popcount(w);
+    int xs = pc;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(xs, d);
+        if (lane >= d) xs += y;
+    }
+    if (lane == kWave - 1) wtot[wave] = xs;
+    __syncthreads();
+    int pre = xs - pc;
+    for (int q = 0; q < wave; ++q) pre += wtot[q];
+    if (tid < NW) spre[tid] = pre;
+    __syncthreads();
+    const int64_t kpref = (int64_t)kpref_t[t];
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+        const int li = r * kClsWG + tid;
+        const int64_t g = c0 + li;
+        if (g < c1) {
+            const unsigned int word = sw[li >> 5];
+            const int bit = li & 31;
+            const int kr = spre[li >> 5] + __builtin_popcount(word & ((1u << bit) - 1u));
+            int64_t pos;
+            if ((word >> bit) & 1u) pos = kpref + kr;
+            else pos = n - 1 - ((c0 - kpref) + (li - kr));
+            if (pos >= 0 && pos < n) s1[pos] = x[r];
+        }
+    }
+}
+
+// Verification and job of the outlier path (one workgroup, after classify).
+// The kept keys form one sorted sequence iff every tile's first kept key is
+// at least the last kept key of the nearest earlier tile that kept any.
+// Then the job is OUTLIER with m = n - kept outliers when m <= n/2;
+// otherwise GENERAL (the user buffer has not been written yet).
+constexpr int kVerWG = 1024;
+
+__global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
+                                                   const unsigned long long* tlast, const unsigned long long* tcount,
+                                                   unsigned long long* kpref_t, int64_t T_sort) {
+    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+    __shared__ unsigned long long s_last[kVerWG];
+    __shared__ int s_has[kVerWG];
+    __shared__ unsigned long long s_kept[kVerWG / kWave];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_bad = 0;
+    const int64_t per = (ntiles + kVerWG - 1) / kVerWG;
+    const int64_t t0 = (int64_t)tid * per;
+    const int64_t t1 = (t0 + per) < ntiles ? (t0 + per) : ntiles;
+    // own chunk: joins inside it, kept total, last kept key
+    unsigned long long kept = 0, last = 0;
+    bool has = false, bad = false;
+    unsigned long long first_of_chunk = 0;
+    bool chunk_first_set = false;
+    for (int64_t tb = t0; tb < t1; tb += 8) {
+        unsigned long long cv[8], fv[8], lv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t t = tb + q;
+            cv[q] = t < t1 ? tcount[t] : 0ull;
+            fv[q] = t < t1 ? tfirst[t] : 0ull;
+            lv[q] = t < t1 ? tlast[t] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (cv[q] == 0) continue;
+            if (has && fv[q] < last) bad = true;
+            if (!chunk_first_set) {
+                chunk_first_set = true;
+                first_of_chunk = fv[q];
+            }
+            has = true;
+            last = lv[q];
+            kept += cv[q];
+        }
+    }
+    s_last[tid] = last;
+    s_has[tid] = has ? 1 : 0;
+    // exclusive prefix of the kept counts over the chunks (wave scan + waves)
+    const int lane = (int)__lane_id();
+    unsigned long long xs = kept;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long y = __shfl_up(xs, d);
+        if (lane >= d) xs += y;
+    }
+    if (lane == kWave - 1) s_kept[tid / kWave] = xs;
+    __syncthreads();
+    unsigned long long pre = xs - kept;
+    for (int q = 0; q < tid / kWave; ++q) pre += s_kept[q];
+    for (int64_t tb = t0; tb < t1; tb += 8) {
+        unsigned long long cv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cv[q] = tb + q < t1 ? tcount[tb + q] : 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (tb + q < t1) kpref_t[tb + q] = pre;
+            pre += cv[q];
+        }
+    }
+    // join with the nearest earlier chunk that kept any key
+    if (chunk_first_set) {
+        for (int u = tid - 1; u >= 0; --u) {
+            if (s_has[u]) {
+                if (first_of_chunk < s_last[u]) bad = true;
+                break;
+            }
+        }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long total = 0;
+        for (int w = 0; w < kVerWG / kWave; ++w) total += s_kept[w];
+        const bool fail = s_bad != 0 || ld_agent(&ctl->bad_join) != 0 || total > (unsigned long long)n;
+        const int64_t m = n - (int64_t)total;
+        if (fail || m > n / 2) {
+            ctl->path = SR_PATH_GENERAL;
+            ctl->m = 0;
+            ctl->job_passes = 0;
+        } else {
+            ctl->m = (unsigned long long)m;
+            ctl->job_passes = ceil_log2_dev((m + T_sort - 1) / T_sort);
+        }
+        ctl->n_kept = total;
+        ctl->reserved[2] = fail ? 1 : 0;
+        ctl->reserved[3] = (unsigned long long)m;
+        ctl->ticket2 = 0;
+        ctl->bad_join = 0;
+    }
 }
 
 // Probe.  The array's neighbour pairs (i, i+1) are cut into probe tiles of
@@ -242,7 +647,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             d += sdn;
             a += san;
             if (d && a) {
-                atomicOr(&ctl->mixed, 1u);
+                if (ld_agent(&ctl->mixed) == 0u) atomicOr(&ctl->mixed, 1u);
                 skip = 1;
             }
         }
@@ -267,7 +672,17 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         slots[blockIdx.x * 4 + 2] = t2;
         slots[blockIdx.x * 4 + 3] = t3;
         __threadfence();
-        last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+        // two-level ticket: groups of kProbeGroup workgroups share a counter
+        // (each on its own 256-byte line), the last of a group bumps ctl->ticket
+        const unsigned int groups = (gridDim.x + kProbeGroup - 1) / kProbeGroup;
+        const unsigned int g = blockIdx.x / kProbeGroup;
+        const unsigned int in_g = g + 1 < groups ? kProbeGroup : gridDim.x - g * kProbeGroup;
+        unsigned int* gc = reinterpret_cast<unsigned int*>(slots + kProbeMaxGrid * 4) + g * 64;
+        last = false;
+        if (atomicAdd(gc, 1u) == in_g - 1) {
+            *gc = 0u;  // reset for the next call (no other workgroup of this group touches it again)
+            last = atomicAdd(&ctl->ticket, 1u) == groups - 1;
+        }
     }
     __syncthreads();
     if (last) {
@@ -300,16 +715,17 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         ctl->path = path;
         ctl->reserved[0] = desc;   // kept for sr_last_stats
         ctl->reserved[1] = asc;
-        ctl->desc = 0;
-        ctl->asc = 0;
-        ctl->sample_desc = 0;
-        ctl->sample_pairs = 0;
+        ctl->reserved[2] = 0;
+        ctl->reserved[3] = 0;
         ctl->mixed = 0;
         ctl->ticket = 0;
-        ctl->n_out = 0;
+        ctl->m = 0;
+        ctl->job_passes = 0;
         ctl->n_kept = 0;
         ctl->bad_join = 0;
         ctl->ticket2 = 0;
+        unsigned int ep = (ctl->epoch + 1u) & 0xFFFFFFu;
+        ctl->epoch = ep == 0u ? 1u : ep;
     }
 }
 
@@ -414,6 +830,7 @@ std::mutex g_mu;
 int g_force_path = -1;
 bool g_profile = false;
 int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
+bool g_outlier_enabled = true;                   // allow the OUTLIER path for keys-only sorts
 
 struct ProfRec {
     std::string name;
@@ -455,14 +872,23 @@ struct ProfScope {
     }
 };
 
+// Per (device, stream): a header allocated once and never moved (control
+// block with the call epoch, probe slots), the data scratch (grown on
+// demand) and the zero-initialised look-back arrays of the outlier path
+// (grown on demand; their status words are stamped with the epoch, which
+// therefore must never restart while they live).
 struct Workspace {
+    void* hdr = nullptr;
     void* base = nullptr;
     size_t bytes = 0;
     Ctl* ctl = nullptr;
-    int force = -2;  // force_path value last written to ctl
+    int force = -2;       // force_path value last written to ctl
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
 };
 
 struct LastCall {
+    int64_t tile = 0;
     int64_t n = 0;
     int es = 0;
     int merge_passes = 0;
@@ -477,12 +903,19 @@ std::map<hipStream_t, LastCall> g_last;
 constexpr size_t kCtlBytes = 256;
 constexpr size_t kHdrBytes = 64 * 1024;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
-static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 <= kHdrBytes, "probe slots");
+static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 + (kProbeMaxGrid / kProbeGroup + 1) * 256 <= kHdrBytes,
+              "probe slots and group counters");
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Workspace of at least `data_bytes` scratch bytes for (device, stream).
-sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Workspace of at least `data_bytes` scratch bytes and `aux_bytes` of
+// zero-initialised look-back space for (device, stream).
+sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size_t aux_bytes = 0) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -493,7 +926,21 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
         if (!slot) slot = new Workspace();
         ws = slot;
     }
-    const size_t need = kHdrBytes + round_up(data_bytes, 256);
+    if (ws->hdr == nullptr) {
+        e = hipMalloc(&ws->hdr, kHdrBytes);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            return fail(SR_ERR_OUT_OF_MEMORY, "workspace header allocation failed");
+        }
+        ws->ctl = reinterpret_cast<Ctl*>(ws->hdr);
+        hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, st, (unsigned long long*)ws->hdr,
+                           (int64_t)(kHdrBytes / 8));
+        hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, ws->ctl);
+        ws->force = -1;
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "init");
+    }
+    const size_t need = round_up(std::max(data_bytes, (size_t)256), 256);
     if (ws->bytes < need) {
         if (ws->base) {
             e = hipStreamSynchronize(st);
@@ -509,11 +956,26 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
             return fail(SR_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(alloc) + " bytes failed");
         }
         ws->bytes = alloc;
-        ws->ctl = reinterpret_cast<Ctl*>(ws->base);
-        hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, ws->ctl);
-        ws->force = -1;
+    }
+    if (aux_bytes > ws->aux_bytes) {
+        if (ws->aux) {
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            hipFree(ws->aux);
+            ws->aux = nullptr;
+            ws->aux_bytes = 0;
+        }
+        const size_t alloc = round_up(std::max(aux_bytes, (size_t)1 << 16), 4096);
+        e = hipMalloc(&ws->aux, alloc);
+        if (e != hipSuccess) {
+            hipGetLastError();
+            return fail(SR_ERR_OUT_OF_MEMORY, "look-back allocation of " + std::to_string(alloc) + " bytes failed");
+        }
+        ws->aux_bytes = alloc;
+        hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, st, (unsigned long long*)ws->aux,
+                           (int64_t)(alloc / 8));
         e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "init");
+        if (e != hipSuccess) return hip_fail(e, "zero");
     }
     int force;
     {
@@ -528,9 +990,9 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out) {
     return SR_OK;
 }
 
-void* ws_data(Workspace* ws) { return (char*)ws->base + kHdrBytes; }
+void* ws_data(Workspace* ws) { return ws->base; }
 unsigned long long* ws_slots(Workspace* ws) {
-    return reinterpret_cast<unsigned long long*>((char*)ws->base + kCtlBytes);
+    return reinterpret_cast<unsigned long long*>((char*)ws->hdr + kCtlBytes);
 }
 
 // Resident workgroups of a kernel on the whole device (persistent grids).
@@ -585,7 +1047,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
         // One tile: sort in place, no probe.
         ProfScope ps(st, "tile_sort");
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, st, keys, keys,
-                           pay, pay, n, (const Ctl*)nullptr, 0, keys, pay);
+                           pay, pay, n, 0, (const Ctl*)nullptr);
         SR_LAUNCH_CHECK("tile_sort");
         lc.trivial = 1;
         std::lock_guard<std::mutex> lk(g_mu);
@@ -593,10 +1055,15 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
         return SR_OK;
     }
     const int64_t nchunks = cdiv(n, CH);
+    const bool outlier_ok = !PAIRS && g_outlier_enabled;
+    const int64_t ncls = outlier_ok ? cdiv(n, kClsTC) : 0;
     const size_t co_bytes = round_up((size_t)(nchunks + 2) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
+    const size_t cls_arr = round_up((size_t)ncls * 8, 256);
     Workspace* ws = nullptr;
-    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws);
+    // aux: tile offsets, first/last kept keys, kept counts, kept bit masks
+    const size_t flag_bytes = round_up((size_t)ncls * (kClsTC / 8), 256);
+    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws, 4 * cls_arr + flag_bytes);
     if (s != SR_OK) return s;
     Ctl* ctl = ws->ctl;
     char* wd = static_cast<char*>(ws_data(ws));
@@ -608,17 +1075,40 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     {
         ProfScope ps(st, "probe");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
-        hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, st, (const S*)keys, n, ctl, ws_slots(ws), 0);
+        hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, st, (const S*)keys, n, ctl, ws_slots(ws),
+                           outlier_ok ? 1 : 0);
         SR_LAUNCH_CHECK("probe");
     }
-    S* kbuf[2] = {keys, skeys};
-    uint32_t* pbuf[2] = {pay, spay};
+    if (outlier_ok) {
+        unsigned long long* aux = static_cast<unsigned long long*>(ws->aux);
+        unsigned long long* kpref_t = aux;
+        unsigned long long* tfirst = aux + cls_arr / 8;
+        unsigned long long* tlast = aux + 2 * (cls_arr / 8);
+        unsigned long long* tcount = aux + 3 * (cls_arr / 8);
+        unsigned int* flags = reinterpret_cast<unsigned int*>(aux + 4 * (cls_arr / 8));
+        {
+            ProfScope ps(st, "classify");
+            hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, st, (const S*)keys, n, ctl,
+                               flags, tfirst, tlast, tcount);
+            SR_LAUNCH_CHECK("classify");
+        }
+        {
+            ProfScope ps(st, "verify");
+            hipLaunchKernelGGL(k_verify, dim3(1), dim3(kVerWG), 0, st, ctl, n, ncls,
+                               (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
+                               (const unsigned long long*)tcount, kpref_t, (int64_t)T);
+            SR_LAUNCH_CHECK("verify");
+        }
+        ProfScope ps(st, "scatter");
+        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, st, (const S*)keys, n,
+                           (const Ctl*)ctl, skeys, (const unsigned int*)flags, (const unsigned long long*)kpref_t);
+        SR_LAUNCH_CHECK("scatter");
+    }
     {
-        // GENERAL: tile sort; REVERSED: in-place reversal (same launch)
+        // GENERAL / OUTLIER: tile sort of the job; REVERSED: in-place reversal
         ProfScope ps(st, "tile_sort");
-        const int to = M % 2;
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
-                           keys, kbuf[to], pay, pbuf[to], n, (const Ctl*)ctl, (int)SR_PATH_GENERAL, keys, pay);
+                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl);
         SR_LAUNCH_CHECK("tile_sort");
     }
     if (PAIRS) {
@@ -629,31 +1119,29 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
         SR_LAUNCH_CHECK("regroup");
     }
     for (int k = 0; k < M; ++k) {
-        const int from = (M - k) % 2, to = (M - k - 1) % 2;
-        const int64_t width = (int64_t)T << k;
         if (use_partition) {
-            ProfScope ps(st, "partition");
-            hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, st,
-                               (const S*)kbuf[from], n, width, CH, nchunks, co, (const Ctl*)ctl,
-                               (int)SR_PATH_GENERAL);
-            SR_LAUNCH_CHECK("partition");
-        }
-        ProfScope ps(st, "merge");
-        if (use_partition) {
+            {
+                ProfScope ps(st, "partition");
+                hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, st, keys, skeys,
+                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl);
+                SR_LAUNCH_CHECK("partition");
+            }
+            ProfScope ps(st, "merge");
             auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
-            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, st, (const S*)kbuf[from], kbuf[to],
-                               (const uint32_t*)pbuf[from], pbuf[to], n, width, (const Ctl*)ctl,
-                               (int)SR_PATH_GENERAL, (const int64_t*)co, nchunks);
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, st, keys, skeys, pay, spay, n, M,
+                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl);
+            SR_LAUNCH_CHECK("merge");
         } else {
+            ProfScope ps(st, "merge");
             hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0, st,
-                               (const S*)kbuf[from], kbuf[to], (const uint32_t*)pbuf[from], pbuf[to], n, width,
-                               (const Ctl*)ctl, (int)SR_PATH_GENERAL, (const int64_t*)nullptr);
+                               keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
+            SR_LAUNCH_CHECK("merge");
         }
-        SR_LAUNCH_CHECK("merge");
     }
     lc.trivial = 0;
     lc.ctl = ctl;
+    lc.tile = T;
     std::lock_guard<std::mutex> lk(g_mu);
     g_last[st] = lc;
     return SR_OK;
@@ -757,6 +1245,7 @@ sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nse
     const int es = elem_bytes(dt);
     if (es == 0 || !bytes) return fail(SR_ERR_INVALID_ARGUMENT, "bad argument");
     size_t b = kHdrBytes + round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
+    b += round_up((n / 1024 + 2) * 8, 256) + 4 * round_up((n / 4096 + 1) * 8, 256) + round_up(n / 8 + 512, 256);
     b += round_up((nseg + 1) * 8 * 4, 256);
     *bytes = std::max(b, (size_t)1 << 20);
     return SR_OK;
@@ -786,12 +1275,23 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
         out->path = h.path;
         out->descents = (int64_t)h.reserved[0];
+        double eq = 0;  // read+write passes over n, as a real number
         switch (h.path) {
-        case SR_PATH_SORTED: out->passes = 0; break;
-        case SR_PATH_REVERSED: out->passes = 1; break;
-        case SR_PATH_GENERAL: out->passes = 1 + lc.merge_passes; break;
-        default: out->passes = 1 + lc.merge_passes; break;
+        case SR_PATH_SORTED: eq = 0; break;
+        case SR_PATH_REVERSED: eq = 1; break;
+        case SR_PATH_OUTLIER: {
+            const double m = (double)h.m;
+            out->outliers = (int64_t)h.m;
+            // classify (n read, n written) + outlier sort (tile + P merges on m)
+            // + final merge of kept and outliers (n read, n written)
+            eq = 2.0 + (1.0 + h.job_passes) * m / (double)lc.n;
+            break;
         }
+        default: eq = 1 + lc.merge_passes; break;
+        }
+        out->passes = (int32_t)std::ceil(eq - 1e-9);
+        out->bytes_moved = eq * 2.0 * (double)lc.n * (double)lc.es;
+        return SR_OK;
     }
     out->bytes_moved = (double)out->passes * 2.0 * (double)lc.n * (double)lc.es;
     return SR_OK;
@@ -823,6 +1323,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "partition_min_n") == 0) {
         if (value < 0) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= 0");
         g_partition_min_n = value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "outlier_path") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "outlier_path is 0 or 1");
+        g_outlier_enabled = value != 0;
         return SR_OK;
     }
     if (std::strcmp(name, "profile") == 0) {

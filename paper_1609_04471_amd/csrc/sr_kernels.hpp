@@ -225,22 +225,30 @@ struct MergeChunk {
         uint32_t px[PAIRS ? IT : 1];
     };
 
-    static __device__ __forceinline__ void bounds(const S* src, int64_t n, int64_t width, int64_t out0,
+    // Runs being merged: pairs of width `width` aligned at multiples of
+    // 2*width, or, when split >= 0, the single pair [0, split), [split, n).
+    static __device__ __forceinline__ void bounds(int64_t n, int64_t width, int64_t split, int64_t out0,
                                                   int64_t& gs, int64_t& la, int64_t& lb, int64_t& d0, int64_t& d1) {
-        gs = out0 / (2 * width) * (2 * width);
-        la = (n - gs) < width ? (n - gs) : width;
-        const int64_t rest = n - gs - la;
-        lb = rest < width ? rest : width;
+        if (split >= 0) {
+            gs = 0;
+            la = split;
+            lb = n - split;
+        } else {
+            gs = out0 / (2 * width) * (2 * width);
+            la = (n - gs) < width ? (n - gs) : width;
+            const int64_t rest = n - gs - la;
+            lb = rest < width ? rest : width;
+        }
         d0 = out0 - gs;
         d1 = (d0 + CH) < (la + lb) ? (d0 + CH) : (la + lb);
     }
 
     // Window of the chunk starting at out0 from precomputed co-ranks (co is
     // indexed by chunk number relative to the same array start).
-    static __device__ __forceinline__ void window_from_co(const S* src, int64_t n, int64_t width, int64_t out0,
+    static __device__ __forceinline__ void window_from_co(int64_t n, int64_t width, int64_t split, int64_t out0,
                                                           const int64_t* co, Win& w) {
         int64_t gs, la, lb, d0, d1;
-        bounds(src, n, width, out0, gs, la, lb, d0, d1);
+        bounds(n, width, split, out0, gs, la, lb, d0, d1);
         const int64_t c = out0 / CH;
         const int64_t i0 = co[c];
         const int64_t i1 = d1 == la + lb ? la : co[c + 1];
@@ -253,9 +261,9 @@ struct MergeChunk {
 
     // Same, with the co-ranks searched here by wavefronts 0 and 1.
     static __device__ __forceinline__ void window_search(Smem& sm, const S* src, int64_t n, int64_t width,
-                                                         int64_t out0, Win& w) {
+                                                         int64_t split, int64_t out0, Win& w) {
         int64_t gs, la, lb, d0, d1;
-        bounds(src, n, width, out0, gs, la, lb, d0, d1);
+        bounds(n, width, split, out0, gs, la, lb, d0, d1);
         const int wave = threadIdx.x / kWave;
         if (wave < 2) {
             const int64_t c = corank_wave<C>(src + gs, la, src + gs + la, lb, wave == 0 ? d0 : d1);
@@ -372,10 +380,10 @@ struct MergeChunk {
     // One chunk, start to end.  src/dst/psrc/pdst point at the start of the
     // (segment) array of length n; co (optional) holds precomputed co-ranks.
     static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
-                               int64_t n, int64_t width, int64_t out0, const int64_t* co = nullptr) {
+                               int64_t n, int64_t width, int64_t split, int64_t out0, const int64_t* co) {
         Win w;
-        if (co != nullptr) window_from_co(src, n, width, out0, co, w);
-        else window_search(sm, src, n, width, out0, w);
+        if (co != nullptr) window_from_co(n, width, split, out0, co, w);
+        else window_search(sm, src, n, width, split, out0, w);
         load(src, psrc, w);
         stage(sm.b, w);
         __syncthreads();
@@ -404,11 +412,12 @@ struct MergePersistent {
     };
 
     static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
-                               int64_t n, int64_t width, const int64_t* co, int64_t nchunks) {
+                               int64_t n, int64_t width, int64_t split, const int64_t* co) {
+        const int64_t nchunks = (n + CH - 1) / CH;
         int64_t c = blockIdx.x;
         if (c >= nchunks) return;
         typename MC::Win w;
-        MC::window_from_co(src, n, width, c * CH, co, w);
+        MC::window_from_co(n, width, split, c * CH, co, w);
         MC::load(src, psrc, w);
         int buf = 0;
         for (;;) {
@@ -418,7 +427,7 @@ struct MergePersistent {
             __syncthreads();
             const int64_t cn = c + gridDim.x;
             if (cn < nchunks) {
-                MC::window_from_co(src, n, width, cn * CH, co, w);
+                MC::window_from_co(n, width, split, cn * CH, co, w);
                 MC::load(src, psrc, w);
             }
             U v[IT];
@@ -434,5 +443,97 @@ struct MergePersistent {
         }
     }
 };
+
+// ============================================================ job views
+// The launch sequence is fixed on the host; which data a launch works on is
+// read from the plan in the control block.  GENERAL sorts the user buffer U
+// with ping-pong partner S1 in M merge passes.  OUTLIER sorts the m outliers
+// (stored at S1[n-m, n)) with partner U in P passes, then merge slot P merges
+// the kept keys S1[0, n-m) with the sorted outliers into U.
+template <class S>
+struct PassView {
+    const S* src;
+    S* dst;
+    const uint32_t* psrc;
+    uint32_t* pdst;
+    int64_t n;
+    int64_t width;
+    int64_t split;
+    bool active;
+};
+
+template <class S>
+__device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
+                                                     int64_t n, int M, int64_t T, int k) {
+    PassView<S> v{};
+    v.active = false;
+    v.split = -1;
+    const int path = ld_agent(&ctl->path);
+    if (path == 3 /* SR_PATH_GENERAL */) {
+        const int from = (M - k) & 1;
+        v.src = from ? S1 : U;
+        v.dst = from ? U : S1;
+        v.psrc = from ? PS1 : PU;
+        v.pdst = from ? PU : PS1;
+        v.n = n;
+        v.width = T << k;
+        v.active = true;
+    } else if (path == 2 /* SR_PATH_OUTLIER */) {
+        const int64_t m = (int64_t)ld_agent(&ctl->m);
+        const int P = ld_agent(&ctl->job_passes);
+        S* X0 = S1 + (n - m);
+        if (k < P) {
+            const int from = (P - k) & 1;
+            v.src = from ? U : X0;
+            v.dst = from ? X0 : U;
+            v.n = m;
+            v.width = T << k;
+            v.active = true;
+        } else if (k == P) {
+            v.src = S1;
+            v.dst = U;
+            v.n = n;
+            v.width = n;
+            v.split = n - m;
+            v.active = true;
+        }
+    }
+    return v;
+}
+
+template <class S>
+__device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
+                                                    int64_t n, int M) {
+    PassView<S> v{};
+    v.active = false;
+    v.split = -1;
+    if (ctl == nullptr) {  // single tile: in place
+        v.src = U;
+        v.dst = U;
+        v.psrc = PU;
+        v.pdst = PU;
+        v.n = n;
+        v.active = true;
+        return v;
+    }
+    const int path = ld_agent(&ctl->path);
+    if (path == 3 /* SR_PATH_GENERAL */) {
+        v.src = U;
+        v.dst = (M & 1) ? S1 : U;
+        v.psrc = PU;
+        v.pdst = (M & 1) ? PS1 : PU;
+        v.n = n;
+        v.active = true;
+    } else if (path == 2 /* SR_PATH_OUTLIER */) {
+        const int64_t m = (int64_t)ld_agent(&ctl->m);
+        const int P = ld_agent(&ctl->job_passes);
+        S* X0 = S1 + (n - m);
+        v.src = X0;
+        v.dst = (P & 1) ? U : X0;
+        v.n = m;
+        v.active = true;
+    }
+    return v;
+}
 
 }  // namespace sr

@@ -181,3 +181,76 @@ def test_separate_partition_launch(gpu, n):
         assert np.array_equal(gk, wk) and np.array_equal(gp, wp)
     finally:
         gpu.set_option("partition_min_n", 1 << 22)
+
+
+def _near(n, seed, frac=100, ties=1):
+    """0..n-1 (optionally // ties) with floor(n/frac) disjoint exchanges."""
+    a = (np.arange(n, dtype=np.int64) // ties).astype(np.int32)
+    rng = np.random.default_rng(seed)
+    m = n // frac
+    pos = rng.choice(n, size=2 * m, replace=False)
+    p, q = pos[0::2], pos[1::2]
+    a[p], a[q] = a[q].copy(), a[p].copy()
+    return a
+
+
+@pytest.mark.parametrize("n", [8193, 65_536, 300_007, 2_000_000, 5_000_011])
+def test_outlier_path_nearly_sorted(gpu, n):
+    for seed, (frac, ties) in enumerate([(100, 1), (100, 7), (30, 1), (1000, 3)]):
+        a = _near(n, seed, frac, ties)
+        got = gpu_sort_keys(gpu, a, "int32")
+        assert np.array_equal(got, oracle.sort_keys(a)), (n, frac, ties)
+        st = gpu.last_stats()
+        if frac >= 100:  # ~2% descents: below the probe's 1/16 threshold
+            assert st["path"] == "outlier", st
+            assert 0 < st["outliers"] <= 4 * (n // frac) + 8, st
+        else:            # ~6.7% descents: the probe may choose either path
+            assert st["path"] in ("outlier", "general"), st
+    b = inputs.nearly_sorted_int32(n, seed=5)
+    assert np.array_equal(gpu_sort_keys(gpu, b, "int32"), oracle.sort_keys(b))
+    assert gpu.last_stats()["path"] == "outlier"
+
+
+def test_outlier_path_falls_back(gpu):
+    n = 1_000_003
+    rot = np.concatenate([np.arange(n // 2, n), np.arange(0, n // 2)]).astype(np.int32)
+    assert np.array_equal(gpu_sort_keys(gpu, rot, "int32"), oracle.sort_keys(rot))
+    assert gpu.last_stats()["path"] == "general"     # kept keys not sorted across tiles
+    gpu.set_option("outlier_path", 0)
+    try:
+        a = inputs.nearly_sorted_int32(n, seed=3)
+        assert np.array_equal(gpu_sort_keys(gpu, a, "int32"), oracle.sort_keys(a))
+        assert gpu.last_stats()["path"] == "general"
+    finally:
+        gpu.set_option("outlier_path", 1)
+
+
+def test_outlier_path_other_dtypes(gpu):
+    n = 400_009
+    f = np.sort(inputs.normal_float32(n, seed=8, specials=False))
+    idx = np.random.default_rng(1).choice(n, size=2 * (n // 100), replace=False)
+    f[idx[0::2]], f[idx[1::2]] = f[idx[1::2]].copy(), f[idx[0::2]].copy()
+    f[::997] = np.float32(-0.0)
+    assert np.array_equal(bits(gpu_sort_keys(gpu, f, "float32")), bits(oracle.sort_keys(f)))
+    u = np.arange(n, dtype=np.uint64) * np.uint64(3) + np.uint64(2**63)
+    u[idx[0::2]], u[idx[1::2]] = u[idx[1::2]].copy(), u[idx[0::2]].copy()
+    assert np.array_equal(gpu_sort_keys(gpu, u, "uint64"), oracle.sort_keys(u))
+    assert gpu.last_stats()["path"] == "outlier"
+
+
+def test_pairs_persistent_merge_large(gpu):
+    n = 4_500_001  # above the partition threshold: persistent merge for 32-bit pairs
+    k = inputs.few_unique_int32(n, seed=77)
+    p = np.arange(n, dtype=np.uint32)
+    gk, gp = gpu_sort_pairs(gpu, k, p, "int32")
+    wk, wp = oracle.sort_pairs(k, p)
+    assert np.array_equal(gk, wk) and np.array_equal(gp, wp)
+
+
+def test_outlier_path_across_workspace_growth(gpu):
+    """Regression: growing the scratch between calls must not disturb the
+    look-back status words of the outlier path (they are epoch-stamped)."""
+    for n in (100_000, 262_144, 400_000, 600_000, 1_000_001, 262_144):
+        a = inputs.int32_of_type("nearly", n, 1003 + n)
+        assert np.array_equal(gpu_sort_keys(gpu, a, "int32"), oracle.sort_keys(a)), n
+        assert gpu.last_stats()["path"] == "outlier", n
