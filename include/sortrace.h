@@ -131,6 +131,10 @@ const char *sr_last_error_message(void);
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
+ *   "tile_variant" 32-bit keys only: 0 = tile sort by 512 threads x 16 keys
+ *                 (default), 1 = 1024 threads x 8 keys (same 8192-key tile).
+ *   "merge_items"  32-bit keys only, merge passes below partition_min_n:
+ *                 outputs per thread, 16 (default) or 8.
  *   "partition_min_n"  from this n on, every merge pass is preceded by a
  *                 separate Merge Path partition launch; below it each merge
  *                 workgroup searches its own window bounds (default 2^22).

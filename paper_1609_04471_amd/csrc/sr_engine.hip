@@ -764,6 +764,162 @@ __global__ __launch_bounds__(kRevWG) void k_regroup(const typename C::S* keys, u
     }
 }
 
+// ------------------------------------------------------------ segmented
+// Batched sort of independent segments [off[s], off[s+1]) (CSR offsets in
+// device memory).  k_seg_plan (one workgroup) derives each segment's tile
+// count, merge-pass count P_s and merge-chunk count, with prefix sums; the
+// tile-sort launch and the merge slots then walk the concatenated tile /
+// chunk lists persistently (each workgroup a contiguous range), finding the
+// segment of an item by binary search and then advancing linearly.  Every
+// segment is sorted exactly as a plain array would be (tile sort, then P_s
+// level-synchronous merge passes), with its own ping-pong parity so that its
+// last pass lands in the caller's buffer.
+struct SegCtl {
+    long long total_tiles;
+    long long total_chunks;
+    int max_passes;
+    int pad;
+};
+
+constexpr int kSegPlanWG = 1024;
+
+__device__ __forceinline__ int64_t find_seg(const int64_t* pre, int64_t nseg, int64_t item) {
+    // last s with pre[s] <= item (pre is nondecreasing, pre[0] = 0)
+    int64_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kSegPlanWG) void k_seg_plan(const int64_t* off, int64_t nseg, int64_t T, int64_t CH,
+                                                         int64_t* tile_pre, int64_t* chunk_pre, int* seg_passes,
+                                                         SegCtl* sc) {
+    __shared__ long long wt[kSegPlanWG / kWave], wc[kSegPlanWG / kWave];
+    __shared__ int wp[kSegPlanWG / kWave];
+    __shared__ long long carry_t, carry_c;
+    __shared__ int maxp;
+    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / kWave;
+    if (tid == 0) {
+        carry_t = 0;
+        carry_c = 0;
+        maxp = 0;
+    }
+    __syncthreads();
+    for (int64_t b = 0; b < nseg; b += kSegPlanWG) {
+        const int64_t s = b + tid;
+        long long tl = 0, ch = 0;
+        int ps = 0;
+        if (s < nseg) {
+            const int64_t len = off[s + 1] - off[s];
+            tl = (len + T - 1) / T;
+            ps = tl > 1 ? ceil_log2_dev(tl) : 0;
+            ch = ps > 0 ? (len + CH - 1) / CH : 0;
+            seg_passes[s] = ps;
+        }
+        long long xt = tl, xc = ch;
+        int xp = ps;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const long long yt = __shfl_up(xt, d), yc = __shfl_up(xc, d);
+            if (lane >= d) {
+                xt += yt;
+                xc += yc;
+            }
+            const int yp = __shfl_xor(xp, d);
+            xp = xp > yp ? xp : yp;
+        }
+        if (lane == kWave - 1) {
+            wt[wave] = xt;
+            wc[wave] = xc;
+        }
+        if (lane == 0) wp[wave] = xp;
+        __syncthreads();
+        long long pt = carry_t + xt - tl, pc = carry_c + xc - ch;
+        for (int q = 0; q < wave; ++q) {
+            pt += wt[q];
+            pc += wc[q];
+        }
+        if (s < nseg) {
+            tile_pre[s] = pt;
+            chunk_pre[s] = pc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 0; q < kSegPlanWG / kWave; ++q) {
+                carry_t += wt[q];
+                carry_c += wc[q];
+                maxp = maxp > wp[q] ? maxp : wp[q];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        tile_pre[nseg] = carry_t;
+        chunk_pre[nseg] = carry_c;
+        sc->total_tiles = carry_t;
+        sc->total_chunks = carry_c;
+        sc->max_passes = maxp;
+    }
+}
+
+template <class C, int WG, int IT, bool PAIRS>
+__global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
+                                                 const int64_t* off, int64_t nseg, const int64_t* tile_pre,
+                                                 const int* seg_passes, const SegCtl* sc) {
+    using TS = TileSort<C, WG, IT, PAIRS>;
+    __shared__ typename TS::Smem sm;
+    const int64_t total = sc->total_tiles;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = (b0 + per) < total ? (b0 + per) : total;
+    if (b0 >= b1) return;
+    int64_t s = find_seg(tile_pre, nseg, b0);
+    for (int64_t b = b0; b < b1; ++b) {
+        while (tile_pre[s + 1] <= b) ++s;
+        const int64_t so = off[s], len = off[s + 1] - so;
+        const int64_t u = b - tile_pre[s];
+        const int64_t base = so + u * TS::T;
+        const int valid = (int)((len - u * TS::T) < TS::T ? (len - u * TS::T) : TS::T);
+        const bool to_s1 = (seg_passes[s] & 1) != 0;
+        typename C::S* dst = to_s1 ? S1 : U;
+        uint32_t* pdst = to_s1 ? PS1 : PU;
+        TS::run(sm, U + base, dst + base, PAIRS ? PU + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
+        __syncthreads();
+    }
+}
+
+template <class C, int WG, int IT, bool PAIRS>
+__global__ __launch_bounds__(WG) void k_seg_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
+                                                  const int64_t* off, int64_t nseg, const int64_t* chunk_pre,
+                                                  const int* seg_passes, const SegCtl* sc, int64_t T, int k) {
+    using MC = MergeChunk<C, WG, IT, PAIRS>;
+    if (k >= sc->max_passes) return;
+    __shared__ typename MC::Smem sm;
+    const int64_t total = sc->total_chunks;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * per;
+    const int64_t c1 = (c0 + per) < total ? (c0 + per) : total;
+    if (c0 >= c1) return;
+    int64_t s = find_seg(chunk_pre, nseg, c0);
+    for (int64_t c = c0; c < c1; ++c) {
+        while (chunk_pre[s + 1] <= c) ++s;
+        const int P = seg_passes[s];
+        if (k >= P) continue;
+        const int64_t so = off[s], len = off[s + 1] - so;
+        const int from = (P - k) & 1;
+        typename C::S* src = from ? S1 : U;
+        typename C::S* dst = from ? U : S1;
+        uint32_t* psrc = from ? PS1 : PU;
+        uint32_t* pdst = from ? PU : PS1;
+        MC::run(sm, src + so, dst + so, PAIRS ? psrc + so : nullptr, PAIRS ? pdst + so : nullptr, len, T << k, -1,
+                (c - chunk_pre[s]) * MC::CH, nullptr);
+        __syncthreads();
+    }
+}
+
 // Exact counts of descents and ascents (sr_measure).
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_count(const typename C::S* keys, int64_t n,
@@ -831,6 +987,8 @@ int g_force_path = -1;
 bool g_profile = false;
 int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
 bool g_outlier_enabled = true;                   // allow the OUTLIER path for keys-only sorts
+int g_tile_variant = 0;                          // 0: 512 threads x 16 keys, 1: 1024 x 8 (32-bit keys only)
+int g_merge_items = 16;                          // fused merge: outputs per thread (16 or 8, 32-bit keys only)
 
 struct ProfRec {
     std::string name;
@@ -1107,10 +1265,19 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     {
         // GENERAL / OUTLIER: tile sort of the job; REVERSED: in-place reversal
         ProfScope ps(st, "tile_sort");
+        if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
+            if (g_tile_variant == 1) {
+                hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, st, keys,
+                                   skeys, pay, spay, n, M, (const Ctl*)ctl);
+                SR_LAUNCH_CHECK("tile_sort");
+                goto tile_done;
+            }
+        }
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
                            keys, skeys, pay, spay, n, M, (const Ctl*)ctl);
         SR_LAUNCH_CHECK("tile_sort");
     }
+tile_done:
     if (PAIRS) {
         ProfScope ps(st, "regroup");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n, kRevWG * 4), 8192);
@@ -1134,8 +1301,18 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
             SR_LAUNCH_CHECK("merge");
         } else {
             ProfScope ps(st, "merge");
-            hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0, st,
-                               keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
+            bool done = false;
+            if constexpr (sizeof(S) == 4 && !PAIRS && TN::MIT == 16) {
+                if (g_merge_items == 8) {
+                    hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)cdiv(n, TN::MWG * 8)),
+                                       dim3(TN::MWG), 0, st, keys, skeys, pay, spay, n, M, (int64_t)T, k,
+                                       (const Ctl*)ctl);
+                    done = true;
+                }
+            }
+            if (!done)
+                hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0,
+                                   st, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
             SR_LAUNCH_CHECK("merge");
         }
     }
@@ -1144,6 +1321,52 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     lc.tile = T;
     std::lock_guard<std::mutex> lk(g_mu);
     g_last[st] = lc;
+    return SR_OK;
+}
+
+template <class C, bool PAIRS>
+sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, int64_t nseg, hipStream_t st) {
+    using S = typename C::S;
+    using TN = Tune<C, PAIRS>;
+    constexpr int T = TN::TWG * TN::TIT;
+    constexpr int CH = TN::MWG * TN::MIT;
+    S* keys = static_cast<S*>(keys_v);
+    const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
+    const size_t pbytes = PAIRS ? round_up((size_t)n * 4, 256) : 0;
+    const size_t arr = round_up((size_t)(nseg + 1) * 8, 256);
+    Workspace* ws = nullptr;
+    sr_status s = get_workspace(st, kbytes + pbytes + 3 * arr + 256, &ws);
+    if (s != SR_OK) return s;
+    char* wd = static_cast<char*>(ws_data(ws));
+    S* skeys = reinterpret_cast<S*>(wd);
+    uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + kbytes) : nullptr;
+    int64_t* tile_pre = reinterpret_cast<int64_t*>(wd + kbytes + pbytes);
+    int64_t* chunk_pre = reinterpret_cast<int64_t*>(wd + kbytes + pbytes + arr);
+    int* seg_passes = reinterpret_cast<int*>(wd + kbytes + pbytes + 2 * arr);
+    SegCtl* sc = reinterpret_cast<SegCtl*>(wd + kbytes + pbytes + 3 * arr);
+    {
+        ProfScope ps(st, "seg_plan");
+        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kSegPlanWG), 0, st, off, nseg, (int64_t)T, (int64_t)CH, tile_pre,
+                           chunk_pre, seg_passes, sc);
+        SR_LAUNCH_CHECK("seg_plan");
+    }
+    {
+        ProfScope ps(st, "seg_tile_sort");
+        auto kern = k_seg_tile<C, TN::TWG, TN::TIT, PAIRS>;
+        const int64_t grid = std::min<int64_t>(cdiv(n, T) + nseg, resident_blocks(kern, TN::TWG));
+        hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(TN::TWG), 0, st, keys, skeys, pay,
+                           spay, off, nseg, (const int64_t*)tile_pre, (const int*)seg_passes, (const SegCtl*)sc);
+        SR_LAUNCH_CHECK("seg_tile_sort");
+    }
+    const int Mbound = ceil_log2(cdiv(n, T));
+    auto mk = k_seg_merge<C, TN::MWG, TN::MIT, PAIRS>;
+    const int64_t mgrid = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, CH) + nseg, resident_blocks(mk, TN::MWG)));
+    for (int k = 0; k < Mbound; ++k) {
+        ProfScope ps(st, "seg_merge");
+        hipLaunchKernelGGL(mk, dim3((unsigned)mgrid), dim3(TN::MWG), 0, st, keys, skeys, pay, spay, off, nseg,
+                           (const int64_t*)chunk_pre, (const int*)seg_passes, (const SegCtl*)sc, (int64_t)T, k);
+        SR_LAUNCH_CHECK("seg_merge");
+    }
     return SR_OK;
 }
 
@@ -1206,8 +1429,29 @@ sr_status sr_sort_pairs(sr_dtype dt, void* keys, uint32_t* payload, size_t n, vo
 sr_status sr_sort_segmented(sr_dtype dt, void* keys, uint32_t* payload, size_t n, const int64_t* offsets,
                             size_t nseg, void* stream) {
     g_err.clear();
-    (void)dt; (void)keys; (void)payload; (void)n; (void)offsets; (void)nseg; (void)stream;
-    return fail(SR_ERR_UNSUPPORTED, "segmented sort not built yet");
+    sr_status s = check_keys(dt, keys, n);
+    if (s != SR_OK) return s;
+    if (nseg == 0 || n <= 1) return SR_OK;
+    if (offsets == nullptr) return fail(SR_ERR_INVALID_ARGUMENT, "offsets is NULL");
+    if ((uintptr_t)offsets & 7u) return fail(SR_ERR_INVALID_ARGUMENT, "offsets not 8-byte aligned");
+    if (nseg > ((size_t)1 << 31)) return fail(SR_ERR_INVALID_ARGUMENT, "too many segments");
+    if (payload && ((uintptr_t)payload & 3u)) return fail(SR_ERR_INVALID_ARGUMENT, "payload not 4-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nn = (int64_t)n, ns = (int64_t)nseg;
+    if (payload) {
+        switch (dt) {
+        case SR_INT32: return seg_impl<CodecI32, true>(keys, payload, nn, offsets, ns, st);
+        case SR_FLOAT32: return seg_impl<CodecF32, true>(keys, payload, nn, offsets, ns, st);
+        case SR_UINT64: return seg_impl<CodecU64, true>(keys, payload, nn, offsets, ns, st);
+        }
+    } else {
+        switch (dt) {
+        case SR_INT32: return seg_impl<CodecI32, false>(keys, nullptr, nn, offsets, ns, st);
+        case SR_FLOAT32: return seg_impl<CodecF32, false>(keys, nullptr, nn, offsets, ns, st);
+        case SR_UINT64: return seg_impl<CodecU64, false>(keys, nullptr, nn, offsets, ns, st);
+        }
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
 }
 
 sr_status sr_measure(sr_dtype dt, const void* keys, size_t n, int64_t* out_host, void* stream) {
@@ -1323,6 +1567,16 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "partition_min_n") == 0) {
         if (value < 0) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= 0");
         g_partition_min_n = value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "tile_variant") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "tile_variant is 0 or 1");
+        g_tile_variant = (int)value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "merge_items") == 0) {
+        if (value != 8 && value != 16) return fail(SR_ERR_INVALID_ARGUMENT, "merge_items is 8 or 16");
+        g_merge_items = (int)value;
         return SR_OK;
     }
     if (std::strcmp(name, "outlier_path") == 0) {

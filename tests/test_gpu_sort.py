@@ -254,3 +254,19 @@ def test_outlier_path_across_workspace_growth(gpu):
         a = inputs.int32_of_type("nearly", n, 1003 + n)
         assert np.array_equal(gpu_sort_keys(gpu, a, "int32"), oracle.sort_keys(a)), n
         assert gpu.last_stats()["path"] == "outlier", n
+
+
+@pytest.mark.parametrize("tile_variant,merge_items", [(1, 16), (0, 8), (1, 8)])
+def test_tuning_variants_same_bytes(gpu, tile_variant, merge_items):
+    gpu.set_option("tile_variant", tile_variant)
+    gpu.set_option("merge_items", merge_items)
+    try:
+        for n in (5000, 8192, 100_003, 2_000_000):
+            for kind in ("random", "few", "reversed"):
+                a = inputs.int32_of_type(kind, n, n + 11)
+                assert np.array_equal(gpu_sort_keys(gpu, a, "int32"), oracle.sort_keys(a)), (kind, n)
+            f = inputs.normal_float32(n, seed=n)
+            assert np.array_equal(bits(gpu_sort_keys(gpu, f, "float32")), bits(oracle.sort_keys(f)))
+    finally:
+        gpu.set_option("tile_variant", 0)
+        gpu.set_option("merge_items", 16)
