@@ -73,7 +73,8 @@ def main():
     ap.add_argument("--reps", type=int, default=10, help="timed reps per type at 256M")
     ap.add_argument("--no-big", action="store_true", help="skip the n=256M section")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few"],
+    ap.add_argument("--no-seg", action="store_true", help="skip the batched-segments section")
+    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -232,6 +233,59 @@ def main():
         torch.cuda.synchronize()
     result.update(per_type_256M=per_big or None, roofline=roofline, copy_GBps=round(copy_gbps, 1) if copy_gbps else None)
 
+    # ------------------------------------------------------------ batched segments
+    seg = None
+    if not args.no_seg and args.only in (None, "seg"):
+        log("generating 4096 segments")
+        hk, hoff, kinds = inputs.segments_int32(4096, seed=inputs.seed_for(4, 0, 0))
+        nseg = hoff.size - 1
+        pristine = torch.from_numpy(hk).to(dev)
+        off = torch.from_numpy(hoff).to(dev)
+        work = torch.empty_like(pristine)
+        ntot = int(hoff[-1])
+
+        def timed(fn, reps):
+            out = []
+            for _ in range(reps):
+                work.copy_(pristine)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                out.append((a.elapsed_time(b), (time.perf_counter() - t0) * 1e3))
+            return out
+
+        sortrace.set_option("graph", 1)
+        timed(lambda: sortrace.sort_segmented(work, off), 2)        # capture + warm-up
+        bt = timed(lambda: sortrace.sort_segmented(work, off), 10)
+        sortrace.set_option("graph", 0)
+        batched = work.clone()
+        views = [work[int(hoff[i]):int(hoff[i + 1])] for i in range(nseg)]
+
+        def plain():
+            for v in views:
+                if v.numel() > 1:
+                    sortrace.sort_keys(v)
+        timed(plain, 1)
+        pt = timed(plain, 3)
+        same = bool(torch.equal(work, batched))
+        bms = statistics.median([x[0] for x in bt])
+        pms = statistics.median([max(x) for x in pt])
+        seg = {"segments": nseg, "keys": ntot,
+               "batched_graph_ms": round(bms, 4),
+               "batched_Mkeys_s": round(ntot / (bms / 1e3) / 1e6, 1),
+               "plain_calls_ms": round(pms, 4),
+               "plain_Mkeys_s": round(ntot / (pms / 1e3) / 1e6, 1),
+               "speedup": round(pms / bms, 2), "identical_results": same}
+        log(f"segments: {seg}")
+        assert same
+        del pristine, work, off, views, batched
+        torch.cuda.synchronize()
+    result["segmented"] = seg
+
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu and args.only is None:
@@ -273,6 +327,7 @@ def main():
         "per_type_2M": result.get("per_type_2M"),
         "per_type_256M": result.get("per_type_256M"),
         "copy_GBps": result.get("copy_GBps"),
+        "segmented_4096": result.get("segmented"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -131,6 +131,13 @@ const char *sr_last_error_message(void);
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
+ *   "graph"       1 = sr_sort_segmented captures its launch sequence in a
+ *                 hipGraph the first time a (dtype, buffers, sizes, stream,
+ *                 options) combination is seen, and replays it afterwards
+ *                 with one hipGraphLaunch (the segment plan is recomputed on
+ *                 the device, so new data and new offsets in the same buffers
+ *                 are handled); 0 = plain launches (default).  sr_sort_keys /
+ *                 sr_sort_pairs always launch directly.
  *   "tile_variant" 32-bit keys only: 0 = tile sort by 512 threads x 16 keys
  *                 (default), 1 = 1024 threads x 8 keys (same 8192-key tile).
  *   "merge_items"  32-bit keys only, merge passes below partition_min_n:

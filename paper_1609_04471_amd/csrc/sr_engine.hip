@@ -1043,6 +1043,7 @@ struct Workspace {
     int force = -2;       // force_path value last written to ctl
     void* aux = nullptr;
     size_t aux_bytes = 0;
+    unsigned long long generation = 0;  // bumped whenever a buffer moves (invalidates captured graphs)
 };
 
 struct LastCall {
@@ -1108,6 +1109,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
             ws->bytes = 0;
         }
         const size_t alloc = std::max(need, (size_t)1 << 20);
+        ws->generation++;
         e = hipMalloc(&ws->base, alloc);
         if (e != hipSuccess) {
             hipGetLastError();
@@ -1123,6 +1125,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
             ws->aux = nullptr;
             ws->aux_bytes = 0;
         }
+        ws->generation++;
         const size_t alloc = round_up(std::max(aux_bytes, (size_t)1 << 16), 4096);
         e = hipMalloc(&ws->aux, alloc);
         if (e != hipSuccess) {
@@ -1187,8 +1190,12 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
         if (e_ != hipSuccess) return hip_fail(e_, what);       \
     } while (0)
 
+// st: the caller's stream (workspace and statistics are kept per stream);
+// ls: the stream the kernels are launched on (st, or a capture stream).
 template <class C, bool PAIRS>
-sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
+sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool prepare_only = false,
+                    hipStream_t ls = nullptr) {
+    if (ls == nullptr) ls = st;
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
     constexpr int T = TN::TWG * TN::TIT;
@@ -1202,9 +1209,10 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     lc.es = (int)sizeof(S) + (PAIRS ? 4 : 0);
     lc.merge_passes = M;
     if (ntiles == 1) {
+        if (prepare_only) return SR_OK;
         // One tile: sort in place, no probe.
-        ProfScope ps(st, "tile_sort");
-        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, st, keys, keys,
+        ProfScope ps(ls, "tile_sort");
+        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, ls, keys, keys,
                            pay, pay, n, 0, (const Ctl*)nullptr);
         SR_LAUNCH_CHECK("tile_sort");
         lc.trivial = 1;
@@ -1222,7 +1230,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     // aux: tile offsets, first/last kept keys, kept counts, kept bit masks
     const size_t flag_bytes = round_up((size_t)ncls * (kClsTC / 8), 256);
     sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws, 4 * cls_arr + flag_bytes);
-    if (s != SR_OK) return s;
+    if (s != SR_OK || prepare_only) return s;
     Ctl* ctl = ws->ctl;
     char* wd = static_cast<char*>(ws_data(ws));
     int64_t* co = reinterpret_cast<int64_t*>(wd);
@@ -1231,9 +1239,9 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
     const bool use_partition = n >= g_partition_min_n;
 
     {
-        ProfScope ps(st, "probe");
+        ProfScope ps(ls, "probe");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
-        hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, st, (const S*)keys, n, ctl, ws_slots(ws),
+        hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
                            outlier_ok ? 1 : 0);
         SR_LAUNCH_CHECK("probe");
     }
@@ -1245,67 +1253,67 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st) {
         unsigned long long* tcount = aux + 3 * (cls_arr / 8);
         unsigned int* flags = reinterpret_cast<unsigned int*>(aux + 4 * (cls_arr / 8));
         {
-            ProfScope ps(st, "classify");
-            hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, st, (const S*)keys, n, ctl,
+            ProfScope ps(ls, "classify");
+            hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n, ctl,
                                flags, tfirst, tlast, tcount);
             SR_LAUNCH_CHECK("classify");
         }
         {
-            ProfScope ps(st, "verify");
-            hipLaunchKernelGGL(k_verify, dim3(1), dim3(kVerWG), 0, st, ctl, n, ncls,
+            ProfScope ps(ls, "verify");
+            hipLaunchKernelGGL(k_verify, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
                                (const unsigned long long*)tcount, kpref_t, (int64_t)T);
             SR_LAUNCH_CHECK("verify");
         }
-        ProfScope ps(st, "scatter");
-        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, st, (const S*)keys, n,
+        ProfScope ps(ls, "scatter");
+        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n,
                            (const Ctl*)ctl, skeys, (const unsigned int*)flags, (const unsigned long long*)kpref_t);
         SR_LAUNCH_CHECK("scatter");
     }
     {
         // GENERAL / OUTLIER: tile sort of the job; REVERSED: in-place reversal
-        ProfScope ps(st, "tile_sort");
+        ProfScope ps(ls, "tile_sort");
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
             if (g_tile_variant == 1) {
-                hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, st, keys,
+                hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
                                    skeys, pay, spay, n, M, (const Ctl*)ctl);
                 SR_LAUNCH_CHECK("tile_sort");
                 goto tile_done;
             }
         }
-        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, st,
+        hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, ls,
                            keys, skeys, pay, spay, n, M, (const Ctl*)ctl);
         SR_LAUNCH_CHECK("tile_sort");
     }
 tile_done:
     if (PAIRS) {
-        ProfScope ps(st, "regroup");
+        ProfScope ps(ls, "regroup");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n, kRevWG * 4), 8192);
-        hipLaunchKernelGGL(k_regroup<C>, dim3(std::max(1u, g)), dim3(kRevWG), 0, st, (const S*)keys, pay, n,
+        hipLaunchKernelGGL(k_regroup<C>, dim3(std::max(1u, g)), dim3(kRevWG), 0, ls, (const S*)keys, pay, n,
                            (const Ctl*)ctl);
         SR_LAUNCH_CHECK("regroup");
     }
     for (int k = 0; k < M; ++k) {
         if (use_partition) {
             {
-                ProfScope ps(st, "partition");
-                hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, st, keys, skeys,
+                ProfScope ps(ls, "partition");
+                hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, ls, keys, skeys,
                                    n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl);
                 SR_LAUNCH_CHECK("partition");
             }
-            ProfScope ps(st, "merge");
+            ProfScope ps(ls, "merge");
             auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
-            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, st, keys, skeys, pay, spay, n, M,
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
                                (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl);
             SR_LAUNCH_CHECK("merge");
         } else {
-            ProfScope ps(st, "merge");
+            ProfScope ps(ls, "merge");
             bool done = false;
             if constexpr (sizeof(S) == 4 && !PAIRS && TN::MIT == 16) {
                 if (g_merge_items == 8) {
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)cdiv(n, TN::MWG * 8)),
-                                       dim3(TN::MWG), 0, st, keys, skeys, pay, spay, n, M, (int64_t)T, k,
+                                       dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                        (const Ctl*)ctl);
                     done = true;
                 }
@@ -1325,7 +1333,9 @@ tile_done:
 }
 
 template <class C, bool PAIRS>
-sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, int64_t nseg, hipStream_t st) {
+sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, int64_t nseg, hipStream_t st,
+                   bool prepare_only = false, hipStream_t ls = nullptr) {
+    if (ls == nullptr) ls = st;
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
     constexpr int T = TN::TWG * TN::TIT;
@@ -1336,7 +1346,7 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     const size_t arr = round_up((size_t)(nseg + 1) * 8, 256);
     Workspace* ws = nullptr;
     sr_status s = get_workspace(st, kbytes + pbytes + 3 * arr + 256, &ws);
-    if (s != SR_OK) return s;
+    if (s != SR_OK || prepare_only) return s;
     char* wd = static_cast<char*>(ws_data(ws));
     S* skeys = reinterpret_cast<S*>(wd);
     uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + kbytes) : nullptr;
@@ -1345,16 +1355,16 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     int* seg_passes = reinterpret_cast<int*>(wd + kbytes + pbytes + 2 * arr);
     SegCtl* sc = reinterpret_cast<SegCtl*>(wd + kbytes + pbytes + 3 * arr);
     {
-        ProfScope ps(st, "seg_plan");
-        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kSegPlanWG), 0, st, off, nseg, (int64_t)T, (int64_t)CH, tile_pre,
+        ProfScope ps(ls, "seg_plan");
+        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kSegPlanWG), 0, ls, off, nseg, (int64_t)T, (int64_t)CH, tile_pre,
                            chunk_pre, seg_passes, sc);
         SR_LAUNCH_CHECK("seg_plan");
     }
     {
-        ProfScope ps(st, "seg_tile_sort");
+        ProfScope ps(ls, "seg_tile_sort");
         auto kern = k_seg_tile<C, TN::TWG, TN::TIT, PAIRS>;
         const int64_t grid = std::min<int64_t>(cdiv(n, T) + nseg, resident_blocks(kern, TN::TWG));
-        hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(TN::TWG), 0, st, keys, skeys, pay,
+        hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(TN::TWG), 0, ls, keys, skeys, pay,
                            spay, off, nseg, (const int64_t*)tile_pre, (const int*)seg_passes, (const SegCtl*)sc);
         SR_LAUNCH_CHECK("seg_tile_sort");
     }
@@ -1362,12 +1372,145 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     auto mk = k_seg_merge<C, TN::MWG, TN::MIT, PAIRS>;
     const int64_t mgrid = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, CH) + nseg, resident_blocks(mk, TN::MWG)));
     for (int k = 0; k < Mbound; ++k) {
-        ProfScope ps(st, "seg_merge");
-        hipLaunchKernelGGL(mk, dim3((unsigned)mgrid), dim3(TN::MWG), 0, st, keys, skeys, pay, spay, off, nseg,
+        ProfScope ps(ls, "seg_merge");
+        hipLaunchKernelGGL(mk, dim3((unsigned)mgrid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, off, nseg,
                            (const int64_t*)chunk_pre, (const int*)seg_passes, (const SegCtl*)sc, (int64_t)T, k);
         SR_LAUNCH_CHECK("seg_merge");
     }
     return SR_OK;
+}
+
+// ------------------------------------------------------------ hipGraphs
+// With the "graph" option on, the launch sequence of a call is captured once
+// per (entry point, dtype, buffers, sizes, stream, options, workspace
+// generation) and replayed afterwards with one hipGraphLaunch.  The plan
+// stays on the device, so a replay adapts to new data in the same buffers.
+bool g_graph = false;
+
+struct GraphKey {
+    int kind, dt, dev;
+    const void *keys, *pay, *off;
+    int64_t n, nseg;
+    hipStream_t st;
+    int64_t opts[6];
+    unsigned long long gen;
+    bool operator<(const GraphKey& o) const {
+        return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
+    }
+};
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// One private capture stream per device (non-blocking, default priority):
+// the legacy null stream cannot be captured.
+hipStream_t capture_stream(int dev) {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = cs;
+    return cs;
+}
+
+template <class Launch, class Prepare>
+sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, const void* off, int64_t n,
+                          int64_t nseg, hipStream_t st, Launch&& launch, Prepare&& prepare) {
+    bool use_graph;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        use_graph = g_graph;
+    }
+    if (!use_graph) return launch(nullptr);
+    sr_status s = prepare();  // allocations happen here, outside any capture
+    if (s != SR_OK) return s;
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.kind = kind;
+    key.dt = dt;
+    hipGetDevice(&key.dev);
+    key.keys = keys;
+    key.pay = pay;
+    key.off = off;
+    key.n = n;
+    key.nseg = nseg;
+    key.st = st;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        key.opts[0] = g_force_path;
+        key.opts[1] = g_partition_min_n;
+        key.opts[2] = g_outlier_enabled;
+        key.opts[3] = g_tile_variant;
+        key.opts[4] = g_merge_items;
+        auto it = g_ws.find({key.dev, st});
+        key.gen = it != g_ws.end() && it->second ? it->second->generation : 0;
+    }
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) exec = it->second;
+    }
+    if (!exec) {
+        bool prof;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            prof = g_profile;
+            g_profile = false;  // no event records inside a captured graph
+        }
+        hipStream_t cs = capture_stream(key.dev);
+        if (cs == nullptr) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_profile = prof;
+            return fail(SR_ERR_DEVICE, "could not create the capture stream");
+        }
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_profile = prof;
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        s = launch(cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_profile = prof;
+        }
+        if (s != SR_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_graphs[key] = exec;
+    }
+    hipError_t e = hipGraphLaunch(exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SR_OK;
+}
+
+// Plain sorts are always launched directly: replays of a captured GENERAL
+// sequence (tile sort feeding the merge passes) gave wrong results on this
+// platform's graph executor, so the "graph" option applies to the segmented
+// entry point only (whose replays are checked against direct launches).
+template <class C, bool PAIRS>
+sr_status sort_dispatch(int dt, void* keys, uint32_t* pay, int64_t n, hipStream_t st) {
+    (void)dt;
+    return sort_impl<C, PAIRS>(keys, pay, n, st);
+}
+
+template <class C, bool PAIRS>
+sr_status seg_dispatch(int dt, void* keys, uint32_t* pay, int64_t n, const int64_t* off, int64_t nseg,
+                       hipStream_t st) {
+    return run_maybe_graph(
+        PAIRS ? 3 : 2, dt, keys, pay, off, n, nseg, st,
+        [&](hipStream_t ls) { return seg_impl<C, PAIRS>(keys, pay, n, off, nseg, st, false, ls); },
+        [&]() { return seg_impl<C, PAIRS>(keys, pay, n, off, nseg, st, true); });
 }
 
 int elem_bytes(sr_dtype dt) {
@@ -1403,9 +1546,9 @@ sr_status sr_sort_keys(sr_dtype dt, void* keys, size_t n, void* stream) {
     if (n <= 1) return SR_OK;
     hipStream_t st = (hipStream_t)stream;
     switch (dt) {
-    case SR_INT32: return sort_impl<CodecI32, false>(keys, nullptr, (int64_t)n, st);
-    case SR_FLOAT32: return sort_impl<CodecF32, false>(keys, nullptr, (int64_t)n, st);
-    case SR_UINT64: return sort_impl<CodecU64, false>(keys, nullptr, (int64_t)n, st);
+    case SR_INT32: return sort_dispatch<CodecI32, false>(dt, keys, nullptr, (int64_t)n, st);
+    case SR_FLOAT32: return sort_dispatch<CodecF32, false>(dt, keys, nullptr, (int64_t)n, st);
+    case SR_UINT64: return sort_dispatch<CodecU64, false>(dt, keys, nullptr, (int64_t)n, st);
     }
     return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
 }
@@ -1419,9 +1562,9 @@ sr_status sr_sort_pairs(sr_dtype dt, void* keys, uint32_t* payload, size_t n, vo
     if (n <= 1) return SR_OK;
     hipStream_t st = (hipStream_t)stream;
     switch (dt) {
-    case SR_INT32: return sort_impl<CodecI32, true>(keys, payload, (int64_t)n, st);
-    case SR_FLOAT32: return sort_impl<CodecF32, true>(keys, payload, (int64_t)n, st);
-    case SR_UINT64: return sort_impl<CodecU64, true>(keys, payload, (int64_t)n, st);
+    case SR_INT32: return sort_dispatch<CodecI32, true>(dt, keys, payload, (int64_t)n, st);
+    case SR_FLOAT32: return sort_dispatch<CodecF32, true>(dt, keys, payload, (int64_t)n, st);
+    case SR_UINT64: return sort_dispatch<CodecU64, true>(dt, keys, payload, (int64_t)n, st);
     }
     return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
 }
@@ -1440,15 +1583,15 @@ sr_status sr_sort_segmented(sr_dtype dt, void* keys, uint32_t* payload, size_t n
     const int64_t nn = (int64_t)n, ns = (int64_t)nseg;
     if (payload) {
         switch (dt) {
-        case SR_INT32: return seg_impl<CodecI32, true>(keys, payload, nn, offsets, ns, st);
-        case SR_FLOAT32: return seg_impl<CodecF32, true>(keys, payload, nn, offsets, ns, st);
-        case SR_UINT64: return seg_impl<CodecU64, true>(keys, payload, nn, offsets, ns, st);
+        case SR_INT32: return seg_dispatch<CodecI32, true>(dt, keys, payload, nn, offsets, ns, st);
+        case SR_FLOAT32: return seg_dispatch<CodecF32, true>(dt, keys, payload, nn, offsets, ns, st);
+        case SR_UINT64: return seg_dispatch<CodecU64, true>(dt, keys, payload, nn, offsets, ns, st);
         }
     } else {
         switch (dt) {
-        case SR_INT32: return seg_impl<CodecI32, false>(keys, nullptr, nn, offsets, ns, st);
-        case SR_FLOAT32: return seg_impl<CodecF32, false>(keys, nullptr, nn, offsets, ns, st);
-        case SR_UINT64: return seg_impl<CodecU64, false>(keys, nullptr, nn, offsets, ns, st);
+        case SR_INT32: return seg_dispatch<CodecI32, false>(dt, keys, nullptr, nn, offsets, ns, st);
+        case SR_FLOAT32: return seg_dispatch<CodecF32, false>(dt, keys, nullptr, nn, offsets, ns, st);
+        case SR_UINT64: return seg_dispatch<CodecU64, false>(dt, keys, nullptr, nn, offsets, ns, st);
         }
     }
     return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
@@ -1567,6 +1710,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "partition_min_n") == 0) {
         if (value < 0) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= 0");
         g_partition_min_n = value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "graph") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "graph is 0 or 1");
+        g_graph = value != 0;
         return SR_OK;
     }
     if (std::strcmp(name, "tile_variant") == 0) {

@@ -87,3 +87,30 @@ def test_segmented_repeat_and_edge(gpu):
     gpu.sort_segmented(t, o, dtype="int32")
     assert np.array_equal(t.cpu().numpy(), oracle.sort_segmented(keys, off))
     gpu.sort_segmented(t, torch.zeros(1, dtype=torch.int64, device=DEV), dtype="int32")
+
+
+def test_graph_replays_match_eager(gpu):
+    """Graph mode: capture once, replay on new data in the same buffers, with
+    eager torch work and synchronizations between replays."""
+    lengths = [3, 9000, 0, 17, 40_000, 8192]
+    off = offsets_of(lengths)
+    n = int(off[-1])
+    t = torch.empty(n, dtype=torch.int32, device=DEV)
+    o = torch.from_numpy(off).to(DEV)
+    plain = torch.empty(300_000, dtype=torch.int32, device=DEV)
+    gpu.set_option("graph", 1)
+    try:
+        for rep in range(4):
+            keys = inputs.random_int32(n, seed=100 + rep)
+            t.copy_(torch.from_numpy(keys))
+            gpu.sort_segmented(t, o, dtype="int32")
+            torch.cuda.synchronize()
+            assert np.array_equal(t.cpu().numpy(), oracle.sort_segmented(keys, off)), rep
+            kind = ("random", "nearly", "reversed", "few")[rep]
+            a = inputs.int32_of_type(kind, plain.numel(), rep)
+            plain.copy_(torch.from_numpy(a))
+            gpu.sort_keys(plain)  # plain sorts launch directly even in graph mode
+            torch.cuda.synchronize()
+            assert np.array_equal(plain.cpu().numpy(), oracle.sort_keys(a)), (rep, kind)
+    finally:
+        gpu.set_option("graph", 0)
