@@ -74,7 +74,9 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the n=256M section")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-seg", action="store_true", help="skip the batched-segments section")
-    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg"],
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -286,6 +288,12 @@ def main():
         torch.cuda.synchronize()
     result["segmented"] = seg
 
+    # ------------------------------------------------------------ serving
+    serving = None
+    if not args.no_serve and args.only in (None, "serve"):
+        serving = serve_section(args, torch, np, inputs, sortrace, dev)
+    result["serving"] = serving
+
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu and args.only is None:
@@ -328,9 +336,90 @@ def main():
         "per_type_256M": result.get("per_type_256M"),
         "copy_GBps": result.get("copy_GBps"),
         "segmented_4096": result.get("segmented"),
+        "serving": result.get("serving"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_section(args, torch, np, inputs, sortrace, dev):
+    """Poisson request stream through the continuous-batching server and the
+    plain one-at-a-time FIFO server (same trace, same device-resident data)."""
+    R = args.serve_requests
+    lo, hi = 1024, 16_777_216
+    pool_n = 1 << 26
+    log("serving: generating request pool")
+    pool_f = torch.from_numpy(inputs.normal_float32(pool_n, seed=inputs.seed_for(5, 1, 0)).view(np.int32)).to(dev)
+    pool_i = torch.from_numpy(inputs.uniform_int32(pool_n, seed=inputs.seed_for(5, 0, 0))).to(dev)
+    u = inputs.unit_double(inputs.stream(inputs.seed_for(5, 2, 0), 3 * R))
+    sizes = np.clip(np.floor(np.exp(np.log(lo) + u[:R] * (np.log(hi) - np.log(lo)))), lo, hi).astype(np.int64)
+    is_f = u[R:2 * R] < 0.5
+    starts = (u[2 * R:] * (pool_n - sizes)).astype(np.int64)
+    offs = np.zeros(R + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    data = torch.empty(int(offs[-1]), dtype=torch.int32, device=dev)
+    views = [data[int(offs[i]):int(offs[i + 1])] for i in range(R)]
+
+    def restore():
+        for i in range(R):
+            src = pool_f if is_f[i] else pool_i
+            views[i].copy_(src[int(starts[i]):int(starts[i] + sizes[i])])
+        torch.cuda.synchronize()
+
+    budget = 4 << 30
+    cfg_batched = dict(streams=4, max_batch_requests=64, max_batch_keys=1 << 26)
+    cfg_plain = dict(streams=1, max_batch_requests=1, max_batch_keys=hi)
+
+    def run(cfg, arrivals):
+        restore()
+        with sortrace.Server(budget, **cfg) as srv:
+            t0 = srv.now() + 0.02
+            for i in range(R):
+                srv.submit(views[i], tag=i, t_arrive=t0 + arrivals[i], dtype="float32" if is_f[i] else "int32")
+            srv.wait_idle(600)
+            recs = srv.records()
+        assert len(recs) == R and all(r["status"] == 0 for r in recs)
+        lat = np.array([r["t_done"] - r["t_arrive"] for r in recs]) * 1e3
+        span = max(r["t_done"] for r in recs) - min(r["t_arrive"] for r in recs)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "throughput_req_s": round(R / span, 1),
+                "Mkeys_s": round(float(sizes.sum()) / span / 1e6, 1),
+                "batches": len({r["batch"] for r in recs})}
+
+    log("serving: closed-loop capacity")
+    closed = run(cfg_batched, np.zeros(R))
+    cap = closed["throughput_req_s"]
+    plain_closed = run(cfg_plain, np.zeros(R))
+    out = {"requests": R, "sizes": f"log-uniform [{lo}, {hi}]", "mean_keys": int(sizes.mean()),
+           "dtypes": "50% float32 N(0,1)+specials, 50% int32 uniform", "hbm_budget_bytes": budget,
+           "batched_config": cfg_batched, "capacity_req_s": cap,
+           "capacity_Mkeys_s": closed["Mkeys_s"], "plain_capacity_req_s": plain_closed["throughput_req_s"],
+           "loads": {}}
+    ea = inputs.unit_double(inputs.stream(inputs.seed_for(5, 3, 0), R))
+    for rho in (0.5, 0.8, 0.95):
+        lam = rho * cap
+        arrivals = np.cumsum(-np.log(1.0 - ea) / lam)
+        b = run(cfg_batched, arrivals)
+        p = run(cfg_plain, arrivals)
+        out["loads"][str(rho)] = {"offered_req_s": round(lam, 1), "batched": b, "plain": p}
+        log(f"serving rho={rho}: batched {b} | plain {p}")
+    # correctness: every request equals the same array sorted alone
+    restore()
+    with sortrace.Server(budget, **cfg_batched) as srv:
+        t0 = srv.now()
+        for i in range(R):
+            srv.submit(views[i], tag=i, t_arrive=t0, dtype="float32" if is_f[i] else "int32")
+        srv.wait_idle(600)
+    mix = data.clone()
+    restore()
+    for i in range(R):
+        sortrace.sort_keys(views[i], dtype="float32" if is_f[i] else "int32")
+    torch.cuda.synchronize()
+    out["alone_equals_mix"] = bool(torch.equal(mix, data))
+    assert out["alone_equals_mix"]
+    del data, pool_f, pool_i, mix
+    torch.cuda.synchronize()
+    return out
 
 
 if __name__ == "__main__":

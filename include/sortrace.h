@@ -101,6 +101,73 @@ sr_status sr_sort_segmented(sr_dtype dt, void *keys, uint32_t *payload, size_t n
                             const int64_t *offsets, size_t nseg, void *stream);
 
 /*
+ * Batched sort of nseg independent arrays, each in its own device buffer:
+ * array s starts at keys_ptrs[s] and has lens[s] keys of type dt.  keys_ptrs
+ * and lens are DEVICE arrays (8-byte aligned) of nseg entries; total is the
+ * sum of lens (known to the caller; it sizes the launch and the scratch).
+ * Each array ends up sorted in place exactly as sr_sort_keys would leave it
+ * (Sec. 1's problem, once per array), all of them in one set of launches.
+ * Keys only.  The lens must sum to total; this is not checked on the device.
+ */
+sr_status sr_sort_batch(sr_dtype dt, void *const *keys_ptrs, const int64_t *lens, size_t nseg, size_t total,
+                        void *stream);
+
+/*
+ * Sizes the workspace of `stream` for keys-only sorts of up to n keys (and
+ * batches of up to nseg arrays), so that later calls up to that size never
+ * allocate or synchronize.  May synchronize `stream` once.
+ */
+sr_status sr_reserve(sr_dtype dt, size_t n, size_t nseg, void *stream);
+
+/* Frees the workspace the library holds for `stream` on the current device
+ * (after synchronizing it).  Call before destroying a stream that sorted. */
+sr_status sr_release_stream(void *stream);
+
+/*
+ * Continuous-batching sort server (serving).  Requests reference keys that
+ * already reside in device memory and carry an arrival time (seconds on the
+ * server's clock, sr_server_now()); submit them in arrival order.  A worker
+ * thread admits arrived requests in FIFO order while the HBM footprint of
+ * admitted, unfinished requests (2 x n x element bytes: keys plus scratch)
+ * stays within hbm_budget_bytes, groups admitted requests of one dtype into a
+ * batch (up to max_batch_requests arrays and max_batch_keys keys) whenever
+ * one of its `streams` streams is idle, and sorts the batch there with
+ * sr_sort_batch (sr_sort_keys for a batch of one).  Batches on different
+ * streams overlap on the device.  streams = 1 with max_batch_requests = 1 is
+ * the plain one-at-a-time FIFO server.  Every result is what sr_sort_keys
+ * gives for the same array alone.
+ */
+typedef struct sr_server sr_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* admission budget for keys + scratch of unfinished requests */
+    int streams;               /* 1..16 batches in flight */
+    int max_batch_requests;    /* arrays per batch (>= 1) */
+    size_t max_batch_keys;     /* keys per batch, also the largest admissible request */
+} sr_server_config;
+
+typedef struct {
+    uint64_t tag;
+    int32_t dtype;
+    int32_t batch;             /* batch id the request ran in */
+    int64_t n;
+    int32_t status;            /* sr_status of its sort */
+    int32_t pad;
+    double t_arrive, t_admit, t_launch, t_done;  /* seconds, server clock; t_done from the batch's completion event */
+} sr_request_record;
+
+sr_status sr_server_create(const sr_server_config *cfg, sr_server **out);
+/* Errors: a request whose footprint exceeds the budget or max_batch_keys, or
+ * an arrival earlier than the previous submission's. */
+sr_status sr_server_submit(sr_server *s, sr_dtype dt, void *keys, size_t n, uint64_t tag, double t_arrive);
+double sr_server_now(sr_server *s);
+/* Waits until every submitted request has finished (SR_ERR_INTERNAL on timeout). */
+sr_status sr_server_wait_idle(sr_server *s, double timeout_s);
+/* Moves up to cap finished requests (completion order) into out (host memory). */
+sr_status sr_server_records(sr_server *s, sr_request_record *out, size_t cap, size_t *count);
+sr_status sr_server_destroy(sr_server *s);
+
+/*
  * Presortedness of keys (Sec. 2): out_host[0] = number of descents
  * a_i > a_{i+1} (Run(A) = descents + 1), out_host[1] = number of ascents
  * a_i < a_{i+1}.  out_host is HOST memory; this call synchronizes `stream`.

@@ -794,20 +794,48 @@ __device__ __forceinline__ int64_t find_seg(const int64_t* pre, int64_t nseg, in
     return lo;
 }
 
-__global__ __launch_bounds__(kSegPlanWG) void k_seg_plan(const int64_t* off, int64_t nseg, int64_t T, int64_t CH,
-                                                         int64_t* tile_pre, int64_t* chunk_pre, int* seg_passes,
-                                                         SegCtl* sc) {
+// off: CSR offsets (nseg+1); or, when lens is not null, per-segment lengths
+// whose exclusive prefix is written to off (nseg+1 entries) here.
+__global__ __launch_bounds__(kSegPlanWG) void k_seg_plan(int64_t* off, const int64_t* lens, int64_t nseg, int64_t T,
+                                                         int64_t CH, int64_t* tile_pre, int64_t* chunk_pre,
+                                                         int* seg_passes, SegCtl* sc) {
     __shared__ long long wt[kSegPlanWG / kWave], wc[kSegPlanWG / kWave];
     __shared__ int wp[kSegPlanWG / kWave];
-    __shared__ long long carry_t, carry_c;
+    __shared__ long long carry_t, carry_c, carry_l;
+    __shared__ long long wl[kSegPlanWG / kWave];
     __shared__ int maxp;
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / kWave;
     if (tid == 0) {
         carry_t = 0;
         carry_c = 0;
+        carry_l = 0;
         maxp = 0;
     }
     __syncthreads();
+    if (lens != nullptr) {
+        // offsets of the segments inside the scratch: exclusive prefix of lens
+        for (int64_t b = 0; b < nseg; b += kSegPlanWG) {
+            const int64_t sg = b + tid;
+            const long long l = sg < nseg ? lens[sg] : 0;
+            long long x = l;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const long long y = __shfl_up(x, d);
+                if (lane >= d) x += y;
+            }
+            if (lane == kWave - 1) wl[wave] = x;
+            __syncthreads();
+            long long pre = carry_l + x - l;
+            for (int q = 0; q < wave; ++q) pre += wl[q];
+            if (sg < nseg) off[sg] = pre;
+            __syncthreads();
+            if (tid == 0)
+                for (int q = 0; q < kSegPlanWG / kWave; ++q) carry_l += wl[q];
+            __syncthreads();
+        }
+        if (tid == 0) off[nseg] = carry_l;
+        __syncthreads();
+    }
     for (int64_t b = 0; b < nseg; b += kSegPlanWG) {
         const int64_t s = b + tid;
         long long tl = 0, ch = 0;
@@ -865,10 +893,13 @@ __global__ __launch_bounds__(kSegPlanWG) void k_seg_plan(const int64_t* off, int
     }
 }
 
+// U is the caller's array and off its CSR offsets; or, when ptrs is not
+// null, segment s lives at ptrs[s] and off holds its place in the scratch.
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
                                                  const int64_t* off, int64_t nseg, const int64_t* tile_pre,
-                                                 const int* seg_passes, const SegCtl* sc) {
+                                                 const int* seg_passes, const SegCtl* sc,
+                                                 typename C::S* const* ptrs) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     __shared__ typename TS::Smem sm;
     const int64_t total = sc->total_tiles;
@@ -884,9 +915,14 @@ __global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S
         const int64_t base = so + u * TS::T;
         const int valid = (int)((len - u * TS::T) < TS::T ? (len - u * TS::T) : TS::T);
         const bool to_s1 = (seg_passes[s] & 1) != 0;
-        typename C::S* dst = to_s1 ? S1 : U;
-        uint32_t* pdst = to_s1 ? PS1 : PU;
-        TS::run(sm, U + base, dst + base, PAIRS ? PU + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
+        if (ptrs != nullptr) {
+            typename C::S* us = ptrs[s] + u * TS::T;
+            TS::run(sm, us, to_s1 ? S1 + base : us, nullptr, nullptr, valid);
+        } else {
+            typename C::S* dst = to_s1 ? S1 : U;
+            uint32_t* pdst = to_s1 ? PS1 : PU;
+            TS::run(sm, U + base, dst + base, PAIRS ? PU + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
+        }
         __syncthreads();
     }
 }
@@ -894,7 +930,8 @@ __global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_seg_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
                                                   const int64_t* off, int64_t nseg, const int64_t* chunk_pre,
-                                                  const int* seg_passes, const SegCtl* sc, int64_t T, int k) {
+                                                  const int* seg_passes, const SegCtl* sc, int64_t T, int k,
+                                                  typename C::S* const* ptrs) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     if (k >= sc->max_passes) return;
     __shared__ typename MC::Smem sm;
@@ -910,11 +947,12 @@ __global__ __launch_bounds__(WG) void k_seg_merge(typename C::S* U, typename C::
         if (k >= P) continue;
         const int64_t so = off[s], len = off[s + 1] - so;
         const int from = (P - k) & 1;
-        typename C::S* src = from ? S1 : U;
-        typename C::S* dst = from ? U : S1;
+        typename C::S* us = ptrs != nullptr ? ptrs[s] : U + so;
+        typename C::S* src = from ? S1 + so : us;
+        typename C::S* dst = from ? us : S1 + so;
         uint32_t* psrc = from ? PS1 : PU;
         uint32_t* pdst = from ? PU : PS1;
-        MC::run(sm, src + so, dst + so, PAIRS ? psrc + so : nullptr, PAIRS ? pdst + so : nullptr, len, T << k, -1,
+        MC::run(sm, src, dst, PAIRS ? psrc + so : nullptr, PAIRS ? pdst + so : nullptr, len, T << k, -1,
                 (c - chunk_pre[s]) * MC::CH, nullptr);
         __syncthreads();
     }
@@ -1332,9 +1370,12 @@ tile_done:
     return SR_OK;
 }
 
+// Offsets mode: keys_v + off (CSR).  Batch mode: ptrs/lens (device arrays)
+// give each segment's own buffer and length; n is then the total.
 template <class C, bool PAIRS>
 sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, int64_t nseg, hipStream_t st,
-                   bool prepare_only = false, hipStream_t ls = nullptr) {
+                   bool prepare_only = false, hipStream_t ls = nullptr, void* const* ptrs = nullptr,
+                   const int64_t* lens = nullptr) {
     if (ls == nullptr) ls = st;
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
@@ -1345,7 +1386,7 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     const size_t pbytes = PAIRS ? round_up((size_t)n * 4, 256) : 0;
     const size_t arr = round_up((size_t)(nseg + 1) * 8, 256);
     Workspace* ws = nullptr;
-    sr_status s = get_workspace(st, kbytes + pbytes + 3 * arr + 256, &ws);
+    sr_status s = get_workspace(st, kbytes + pbytes + 4 * arr + 256, &ws);
     if (s != SR_OK || prepare_only) return s;
     char* wd = static_cast<char*>(ws_data(ws));
     S* skeys = reinterpret_cast<S*>(wd);
@@ -1354,18 +1395,23 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     int64_t* chunk_pre = reinterpret_cast<int64_t*>(wd + kbytes + pbytes + arr);
     int* seg_passes = reinterpret_cast<int*>(wd + kbytes + pbytes + 2 * arr);
     SegCtl* sc = reinterpret_cast<SegCtl*>(wd + kbytes + pbytes + 3 * arr);
+    int64_t* seg_off = reinterpret_cast<int64_t*>(wd + kbytes + pbytes + 3 * arr + 256);
+    int64_t* plan_off = ptrs != nullptr ? seg_off : const_cast<int64_t*>(off);
     {
         ProfScope ps(ls, "seg_plan");
-        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kSegPlanWG), 0, ls, off, nseg, (int64_t)T, (int64_t)CH, tile_pre,
-                           chunk_pre, seg_passes, sc);
+        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kSegPlanWG), 0, ls, plan_off, lens, nseg, (int64_t)T,
+                           (int64_t)CH, tile_pre, chunk_pre, seg_passes, sc);
         SR_LAUNCH_CHECK("seg_plan");
     }
+    off = plan_off;
+    S* const* sptrs = reinterpret_cast<S* const*>(ptrs);
     {
         ProfScope ps(ls, "seg_tile_sort");
         auto kern = k_seg_tile<C, TN::TWG, TN::TIT, PAIRS>;
         const int64_t grid = std::min<int64_t>(cdiv(n, T) + nseg, resident_blocks(kern, TN::TWG));
         hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(TN::TWG), 0, ls, keys, skeys, pay,
-                           spay, off, nseg, (const int64_t*)tile_pre, (const int*)seg_passes, (const SegCtl*)sc);
+                           spay, off, nseg, (const int64_t*)tile_pre, (const int*)seg_passes, (const SegCtl*)sc,
+                           sptrs);
         SR_LAUNCH_CHECK("seg_tile_sort");
     }
     const int Mbound = ceil_log2(cdiv(n, T));
@@ -1374,7 +1420,7 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     for (int k = 0; k < Mbound; ++k) {
         ProfScope ps(ls, "seg_merge");
         hipLaunchKernelGGL(mk, dim3((unsigned)mgrid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, off, nseg,
-                           (const int64_t*)chunk_pre, (const int*)seg_passes, (const SegCtl*)sc, (int64_t)T, k);
+                           (const int64_t*)chunk_pre, (const int*)seg_passes, (const SegCtl*)sc, (int64_t)T, k, sptrs);
         SR_LAUNCH_CHECK("seg_merge");
     }
     return SR_OK;
@@ -1595,6 +1641,79 @@ sr_status sr_sort_segmented(sr_dtype dt, void* keys, uint32_t* payload, size_t n
         }
     }
     return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+}
+
+sr_status sr_sort_batch(sr_dtype dt, void* const* keys_ptrs, const int64_t* lens, size_t nseg, size_t total,
+                        void* stream) {
+    g_err.clear();
+    if (elem_bytes(dt) == 0) return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+    if (nseg == 0 || total == 0) return SR_OK;
+    if (!keys_ptrs || !lens) return fail(SR_ERR_INVALID_ARGUMENT, "keys_ptrs or lens is NULL");
+    if (((uintptr_t)keys_ptrs & 7u) || ((uintptr_t)lens & 7u))
+        return fail(SR_ERR_INVALID_ARGUMENT, "keys_ptrs/lens not 8-byte aligned");
+    if (total > ((size_t)1 << 36) || nseg > ((size_t)1 << 31)) return fail(SR_ERR_INVALID_ARGUMENT, "batch too large");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nn = (int64_t)total, ns = (int64_t)nseg;
+    switch (dt) {
+    case SR_INT32: return seg_impl<CodecI32, false>(nullptr, nullptr, nn, nullptr, ns, st, false, nullptr, keys_ptrs, lens);
+    case SR_FLOAT32: return seg_impl<CodecF32, false>(nullptr, nullptr, nn, nullptr, ns, st, false, nullptr, keys_ptrs, lens);
+    case SR_UINT64: return seg_impl<CodecU64, false>(nullptr, nullptr, nn, nullptr, ns, st, false, nullptr, keys_ptrs, lens);
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+}
+
+sr_status sr_reserve(sr_dtype dt, size_t n, size_t nseg, void* stream) {
+    g_err.clear();
+    if (elem_bytes(dt) == 0) return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nn = (int64_t)std::max<size_t>(n, 2), ns = (int64_t)std::max<size_t>(nseg, 1);
+    sr_status s = SR_OK;
+    switch (dt) {
+    case SR_INT32:
+        s = seg_impl<CodecI32, false>(nullptr, nullptr, nn, nullptr, ns, st, true);
+        if (s == SR_OK) s = sort_impl<CodecI32, false>(nullptr, nullptr, nn, st, true);
+        break;
+    case SR_FLOAT32:
+        s = seg_impl<CodecF32, false>(nullptr, nullptr, nn, nullptr, ns, st, true);
+        if (s == SR_OK) s = sort_impl<CodecF32, false>(nullptr, nullptr, nn, st, true);
+        break;
+    case SR_UINT64:
+        s = seg_impl<CodecU64, false>(nullptr, nullptr, nn, nullptr, ns, st, true);
+        if (s == SR_OK) s = sort_impl<CodecU64, false>(nullptr, nullptr, nn, st, true);
+        break;
+    }
+    return s;
+}
+
+sr_status sr_release_stream(void* stream) {
+    g_err.clear();
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hipGetDevice(&dev);
+    Workspace* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find({dev, st});
+        if (it == g_ws.end()) return SR_OK;
+        ws = it->second;
+        g_ws.erase(it);
+        g_last.erase(st);
+        for (auto gi = g_graphs.begin(); gi != g_graphs.end();) {
+            if (gi->first.st == st && gi->first.dev == dev) {
+                hipGraphExecDestroy(gi->second);
+                gi = g_graphs.erase(gi);
+            } else {
+                ++gi;
+            }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (ws->hdr) hipFree(ws->hdr);
+    if (ws->base) hipFree(ws->base);
+    if (ws->aux) hipFree(ws->aux);
+    delete ws;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return SR_OK;
 }
 
 sr_status sr_measure(sr_dtype dt, const void* keys, size_t n, int64_t* out_host, void* stream) {

@@ -25,15 +25,29 @@ STATUS = {0: "SR_OK", 1: "SR_ERR_INVALID_ARGUMENT", 2: "SR_ERR_UNSUPPORTED",
           3: "SR_ERR_OUT_OF_MEMORY", 4: "SR_ERR_DEVICE", 5: "SR_ERR_INTERNAL"}
 
 # Every symbol include/sortrace.h declares.
-EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_measure",
-           "sr_workspace_bytes", "sr_last_stats", "sr_status_str", "sr_last_error_message",
-           "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe")
+EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch", "sr_reserve",
+           "sr_release_stream", "sr_measure", "sr_workspace_bytes", "sr_last_stats", "sr_status_str",
+           "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
+           "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
+           "sr_server_records", "sr_server_destroy")
 
 
 class SrStats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("passes", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("descents", ctypes.c_int64), ("outliers", ctypes.c_int64),
                 ("bytes_moved", ctypes.c_double)]
+
+
+class SrServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("max_batch_requests", ctypes.c_int), ("max_batch_keys", ctypes.c_size_t)]
+
+
+class SrRequestRecord(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("dtype", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class SortraceError(RuntimeError):
@@ -70,9 +84,19 @@ def load(path: str = LIB_PATH):
     lib.sr_profile_collect.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
     lib.sr_copy_bandwidth_probe.argtypes = [vp, vp, sz, vp]
+    lib.sr_sort_batch.argtypes = [i32, vp, vp, sz, sz, vp]
+    lib.sr_reserve.argtypes = [i32, sz, sz, vp]
+    lib.sr_release_stream.argtypes = [vp]
+    lib.sr_server_create.argtypes = [ctypes.POINTER(SrServerConfig), ctypes.POINTER(vp)]
+    lib.sr_server_submit.argtypes = [vp, i32, vp, sz, ctypes.c_uint64, ctypes.c_double]
+    lib.sr_server_now.argtypes = [vp]
+    lib.sr_server_wait_idle.argtypes = [vp, ctypes.c_double]
+    lib.sr_server_records.argtypes = [vp, ctypes.POINTER(SrRequestRecord), sz, ctypes.POINTER(sz)]
+    lib.sr_server_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("sr_status_str", "sr_last_error_message"):
             getattr(lib, name).restype = i32
+    lib.sr_server_now.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -199,3 +223,67 @@ def copy_probe(dst, src, stream=None) -> None:
     nbytes = src.numel() * src.element_size()
     _check(lib.sr_copy_bandwidth_probe(_dev(dst, "dst"), _dev(src, "src"), nbytes, _stream(stream)),
            "sr_copy_bandwidth_probe")
+
+
+def sort_batch(arrays, dtype: str | None = None, stream=None):
+    """Sort every tensor of ``arrays`` in place, all in one batch of launches."""
+    import torch
+    lib = load()
+    arrays = [a for a in arrays if a.numel() > 0]
+    if not arrays:
+        return
+    dt = _key_dtype(arrays[0], dtype)
+    dev = arrays[0].device
+    ptrs = torch.tensor([_dev(a, "array") for a in arrays], dtype=torch.int64, device=dev)
+    lens = torch.tensor([a.numel() for a in arrays], dtype=torch.int64, device=dev)
+    total = sum(a.numel() for a in arrays)
+    _check(lib.sr_sort_batch(dt, ptrs.data_ptr(), lens.data_ptr(), len(arrays), total, _stream(stream)),
+           "sr_sort_batch")
+    return ptrs, lens  # keep the device arrays alive until the stream has used them
+
+
+class Server:
+    """Continuous-batching sort server (see sr_server_* in include/sortrace.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, streams: int = 4, max_batch_requests: int = 64,
+                 max_batch_keys: int = 1 << 25):
+        self._lib = load()
+        cfg = SrServerConfig(hbm_budget_bytes, streams, max_batch_requests, max_batch_keys)
+        h = ctypes.c_void_p()
+        _check(self._lib.sr_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sr_server_create")
+        self._h = h
+
+    def now(self) -> float:
+        return self._lib.sr_server_now(self._h)
+
+    def submit(self, keys, tag: int, t_arrive: float, dtype: str | None = None):
+        _check(self._lib.sr_server_submit(self._h, _key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(),
+                                          tag, t_arrive), "sr_server_submit")
+
+    def wait_idle(self, timeout_s: float = 60.0):
+        _check(self._lib.sr_server_wait_idle(self._h, timeout_s), "sr_server_wait_idle")
+
+    def records(self) -> list:
+        out = []
+        buf = (SrRequestRecord * 4096)()
+        while True:
+            cnt = ctypes.c_size_t()
+            _check(self._lib.sr_server_records(self._h, buf, 4096, ctypes.byref(cnt)), "sr_server_records")
+            for i in range(cnt.value):
+                r = buf[i]
+                out.append({"tag": r.tag, "dtype": r.dtype, "batch": r.batch, "n": r.n, "status": r.status,
+                            "t_arrive": r.t_arrive, "t_admit": r.t_admit, "t_launch": r.t_launch,
+                            "t_done": r.t_done})
+            if cnt.value < 4096:
+                return out
+
+    def close(self):
+        if self._h:
+            self._lib.sr_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
