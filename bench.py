@@ -307,7 +307,7 @@ def main():
                 done += N_SMALL
             rounds += 1
             el = time.perf_counter() - t0
-            if el > 10.0 or rounds >= 8:
+            if el > 12.0 or rounds >= 40:
                 break
         cpu = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": 1, "kind": "oracle",
                "sample": f"{rounds} round(s) of the four 2M int32 inputs ({done} keys) through the "

@@ -205,10 +205,11 @@ const char *sr_last_error_message(void);
  *                 the device, so new data and new offsets in the same buffers
  *                 are handled); 0 = plain launches (default).  sr_sort_keys /
  *                 sr_sort_pairs always launch directly.
- *   "tile_variant" 32-bit keys only: 0 = tile sort by 512 threads x 16 keys
- *                 (default), 1 = 1024 threads x 8 keys (same 8192-key tile).
+ *   "tile_variant" 32-bit keys only: 0 = tile sort by 512 threads x 16 keys,
+ *                 1 = 1024 threads x 8 keys (same 8192-key tile), -1 = 1
+ *                 below partition_min_n and 0 from it on (default).
  *   "merge_items"  32-bit keys only, merge passes below partition_min_n:
- *                 outputs per thread, 16 (default) or 8.
+ *                 outputs per thread, 8 (default) or 16.
  *   "partition_min_n"  from this n on, every merge pass is preceded by a
  *                 separate Merge Path partition launch; below it each merge
  *                 workgroup searches its own window bounds (default 2^22).

@@ -1025,8 +1025,8 @@ int g_force_path = -1;
 bool g_profile = false;
 int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
 bool g_outlier_enabled = true;                   // allow the OUTLIER path for keys-only sorts
-int g_tile_variant = 0;                          // 0: 512 threads x 16 keys, 1: 1024 x 8 (32-bit keys only)
-int g_merge_items = 16;                          // fused merge: outputs per thread (16 or 8, 32-bit keys only)
+int g_tile_variant = -1;  // -1 auto (1024 x 8 below partition_min_n), 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
+int g_merge_items = 8;    // fused merge: outputs per thread (16 or 8, 32-bit keys only)
 
 struct ProfRec {
     std::string name;
@@ -1312,7 +1312,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         // GENERAL / OUTLIER: tile sort of the job; REVERSED: in-place reversal
         ProfScope ps(ls, "tile_sort");
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
-            if (g_tile_variant == 1) {
+            if (g_tile_variant == 1 || (g_tile_variant == -1 && !use_partition)) {
                 hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
                                    skeys, pay, spay, n, M, (const Ctl*)ctl);
                 SR_LAUNCH_CHECK("tile_sort");
@@ -1358,7 +1358,7 @@ tile_done:
             }
             if (!done)
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0,
-                                   st, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
+                                   ls, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
             SR_LAUNCH_CHECK("merge");
         }
     }
@@ -1837,7 +1837,7 @@ sr_status sr_set_option(const char* name, int64_t value) {
         return SR_OK;
     }
     if (std::strcmp(name, "tile_variant") == 0) {
-        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "tile_variant is 0 or 1");
+        if (value < -1 || value > 1) return fail(SR_ERR_INVALID_ARGUMENT, "tile_variant is -1, 0 or 1");
         g_tile_variant = (int)value;
         return SR_OK;
     }

@@ -256,7 +256,7 @@ def test_outlier_path_across_workspace_growth(gpu):
         assert gpu.last_stats()["path"] == "outlier", n
 
 
-@pytest.mark.parametrize("tile_variant,merge_items", [(1, 16), (0, 8), (1, 8)])
+@pytest.mark.parametrize("tile_variant,merge_items", [(1, 16), (0, 8), (0, 16), (1, 8)])
 def test_tuning_variants_same_bytes(gpu, tile_variant, merge_items):
     gpu.set_option("tile_variant", tile_variant)
     gpu.set_option("merge_items", merge_items)
@@ -268,5 +268,5 @@ def test_tuning_variants_same_bytes(gpu, tile_variant, merge_items):
             f = inputs.normal_float32(n, seed=n)
             assert np.array_equal(bits(gpu_sort_keys(gpu, f, "float32")), bits(oracle.sort_keys(f)))
     finally:
-        gpu.set_option("tile_variant", 0)
-        gpu.set_option("merge_items", 16)
+        gpu.set_option("tile_variant", -1)
+        gpu.set_option("merge_items", 8)
