@@ -59,7 +59,11 @@ typedef enum {
     SR_PATH_SORTED = 0,    /* already nondecreasing: nothing written */
     SR_PATH_REVERSED = 1,  /* nonincreasing: reversed in place (stable for pairs) */
     SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back */
-    SR_PATH_GENERAL = 3    /* tile sort + merge passes */
+    SR_PATH_GENERAL = 3,   /* tile sort + merge passes */
+    SR_PATH_RUNS = 4       /* natural runs (keys only): descending runs reversed in
+                              place, disordered tiles sorted, runs whose values are
+                              already in order joined, then a merge tree over the
+                              remaining leaves (Sec. 3 natural runs, Sec. 2 Mono) */
 } sr_path;
 
 typedef struct {
@@ -71,6 +75,9 @@ typedef struct {
     int64_t descents;      /* probe: descents seen (exact when path is SORTED/REVERSED) */
     int64_t outliers;      /* OUTLIER path: keys moved to the outlier list */
     double bytes_moved;    /* algorithmic HBM bytes: unrounded passes x 2 x n x element bytes */
+    int64_t run_leaves;    /* RUNS path: sorted leaves left after the in-order joins */
+    int32_t merge_passes;  /* merge passes of the chosen path (RUNS: over its leaves) */
+    int32_t pad;
 } sr_stats;
 
 /*
@@ -198,6 +205,10 @@ const char *sr_last_error_message(void);
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
+ *   "runs_path"   1 = keys-only sorts may take SR_PATH_RUNS (default); 0 = never.
+ *                 A forced SR_PATH_RUNS still falls back to SR_PATH_GENERAL
+ *                 when the run plan exceeds its limits (4096 runs and dense
+ *                 pieces, 2048 leaves, half the keys in dense tiles).
  *   "graph"       1 = sr_sort_segmented captures its launch sequence in a
  *                 hipGraph the first time a (dtype, buffers, sizes, stream,
  *                 options) combination is seen, and replays it afterwards

@@ -72,6 +72,7 @@ struct Ctl {
     int job_passes;                   // OUTLIER: merge passes of the outlier sort
     int pad0;
     unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
+    unsigned long long run[4];        // RUNS: merge leaves, merge passes, keys reversed, keys in dense pieces
 };
 
 // Plain relaxed agent-scope accessors (coherent across the XCDs' L2s).

@@ -63,6 +63,578 @@ __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
     return ctl == nullptr || ld_agent(&ctl->path) == want;
 }
 
+// Outlier-path tile geometry (used by the RUNS job too).
+constexpr int kClsWG = 256;
+constexpr int kClsPer = 17;
+constexpr int kClsW = kClsWG * kClsPer;  // 4352-key window
+constexpr int kClsTC = 4096;             // core keys per tile
+constexpr int kClsH = (kClsW - kClsTC) / 2;
+constexpr int kClsMaxIter = 48;
+
+__device__ __forceinline__ int ceil_log2_dev(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
+}
+
+constexpr int kVerWG = 1024;
+
+// ------------------------------------------------------------ natural runs
+// RUNS job: the natural runs of natural mergesort (Sec. 3) found in parallel,
+// descending ones reversed in place, and a merge tree over the resulting
+// sorted leaves, so presorted input skips most merge passes.  The measure it
+// exploits is Mono (Sec. 2): the fewest monotone pieces of the array.
+//
+// Pair i is (key i, key i+1); it is strict when the two keys differ.  A
+// turning is a strict pair i whose nearest earlier strict pair j points the
+// other way; the keys j+1 .. i between them (equal keys) form its block, the
+// peak or valley.  Every turning places one run boundary inside its block:
+// the block joins the descending side (boundary at j+1 for a peak, at i+1 for
+// a valley) unless that descending stretch is a single strict pair, which is
+// then dropped instead (boundary at i+1 for the peak, j+1 for the valley --
+// the same position).  Equal positions are kept once.  Each run then holds
+// strict pairs of one direction only, so it is monotone; the count matches
+// Mono on the teeth classes of Sec. 2, and on k-sharp teeth every descending
+// section becomes one run whose reversal continues its neighbours.
+//
+// Launch order (the same fixed launches as the outlier path):
+//   classify  per 4096-key tile: heads (at most kRunHeads, else the tile is
+//             dense), first/last strict direction, min and max (runscan_lds)
+//   verify    one workgroup: carries across tiles, the head list, singleton
+//             joins, dense tiles as sorted pieces, in-order joins of adjacent
+//             leaves (max of one <= min of the next), merge-tree pass count
+//             and per-pass chunk prefixes; keeps RUNS only when it is cheaper
+//             than the other paths (run_plan)
+//   scatter   reverses the descending runs in place (runs_reverse)
+//   tile sort sorts the dense pieces in place
+//   merges    pass k merges leaf groups of 2^(k+1) leaves; one extra copy
+//             pass when the pass count is odd lands the result in U
+constexpr int kRunHeads = 8;           // turnings recorded per 4096-key tile; more: dense
+constexpr int kRunMaxBase = 4096;      // runs and dense pieces a plan may hold
+constexpr int kRunMaxLeaves = 2048;    // merge leaves after in-order joins
+constexpr int kRunMaxPasses = 16;
+constexpr int kRevPairs = 2048;        // key pairs swapped per reversal work unit
+constexpr int kRevPer = kRevPairs / kClsWG;
+
+struct RunTile {
+    int nh;                         // turnings recorded, or -1: dense tile
+    int fz;                         // tile-relative index of the first strict pair, -1 if none
+    int lz;                         // tile-relative index of the last strict pair, -1 if none
+    int signs;                      // bit 0: first strict pair descends; bit 1: last one does
+    int heads[kRunHeads];           // turnings (i << 13 | j << 1 | descending), tile-relative i, j
+    unsigned long long vmin, vmax;  // encoded extremes of the tile's keys
+};
+static_assert(sizeof(RunTile) == 64, "run descriptor is one 64-byte record");
+
+// Plan of a RUNS sort.  Entries and boundaries pack a position with its kind
+// in the top byte: 0 array start, 1 run boundary of a turning, 2 dense piece
+// start, 3 end of a dense piece; entries use 4 for a valley and 5 for a peak
+// (position i, with j in ent_j).
+struct RunArea {
+    long long L;        // merge leaves
+    long long nbase;    // runs and dense pieces
+    long long ndesc;    // descending runs
+    long long nrev;     // reversal work units
+    int npasses;        // merge passes (P, plus one copy pass when P is odd)
+    int P;
+    int pad0, pad1;
+    long long pbase[kRunMaxPasses];    // pass k: its chunk prefix starts at pre[pbase[k]]
+    long long ptotal[kRunMaxPasses];   // pass k: chunks
+    long long lb[kRunMaxLeaves + 1];   // merge leaf starts, lb[L] = n
+    long long pre[2 * kRunMaxLeaves + 2 * kRunMaxPasses];
+    long long ent[kRunMaxBase + 2];    // turnings and dense markers in array order
+    long long ent_j[kRunMaxBase + 2];
+    long long bs[kRunMaxBase + 2];     // leaf boundaries
+    unsigned long long bmin[kRunMaxBase], bmax[kRunMaxBase];
+    long long ds[kRunMaxBase], de[kRunMaxBase];  // descending runs [ds, de)
+    long long dpre[kRunMaxBase + 1];             // reversal units before descending run i
+};
+
+constexpr long long kPosMask = (1LL << 56) - 1;
+__device__ __forceinline__ long long bpos(long long b) { return b & kPosMask; }
+__device__ __forceinline__ int bkind(long long b) { return (int)(b >> 56); }
+
+// Latest nonzero value among lanes 0..lane (0 if none): a scan with the
+// associative "later nonzero wins".
+__device__ __forceinline__ int wave_last_nonzero(int x) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o && x == 0) x = y;
+    }
+    return x;
+}
+
+// Exclusive prefix of v over the workgroup's threads in order, and the total.
+// s_w holds one value per wavefront.
+__device__ __forceinline__ long long wg_scan_excl(long long v, long long* s_w, long long& total) {
+    const int lane = (int)__lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    long long x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) s_w[wave] = x;
+    __syncthreads();
+    long long pre = x - v, tot = 0;
+    for (int q = 0; q < nw; ++q) {
+        if (q < wave) pre += s_w[q];
+        tot += s_w[q];
+    }
+    total = tot;
+    return pre;
+}
+
+// Run descriptor of the 4096-key tile [c0, c1) from its window in LDS (sk[0]
+// is key w0; the window reaches key c1 when c1 < n).  Every thread of the
+// 256-thread workgroup takes 16 consecutive pairs.  A pair's previous strict
+// pair comes from a max-scan of ((index + 1) << 1 | descending); the tile's
+// first strict pair has its previous one in an earlier tile, so the plan
+// decides whether it turns.
+template <class U>
+__device__ void runscan_lds(const U* sk, int64_t n, int64_t c0, int64_t c1, int64_t w0, RunTile* out) {
+    constexpr int PER = kClsTC / kClsWG;
+    constexpr int NW = kClsWG / kWave;
+    __shared__ int s_last[NW], s_cnt[NW], s_first;
+    __shared__ U s_mn[NW], s_mx[NW];
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    if (tid == 0) s_first = -1;
+    const int64_t qend = c1 < n - 1 ? c1 : n - 1;  // pairs of this tile: [c0, qend)
+    const int b0 = tid * PER;
+    int d[PER];
+    int lastv = 0, firstv = 0;
+    U mn = ~(U)0, mx = 0;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const int64_t q = c0 + b0 + r;
+        int sg = 0;
+        if (q < c1) {
+            const U a = sk[q - w0];
+            mn = a < mn ? a : mn;
+            mx = a > mx ? a : mx;
+            if (q < qend) {
+                const U b = sk[q - w0 + 1];
+                sg = a < b ? 1 : (a > b ? -1 : 0);
+            }
+        }
+        d[r] = sg;
+        if (sg != 0) {
+            lastv = ((b0 + r + 1) << 1) | (sg < 0 ? 1 : 0);
+            if (firstv == 0) firstv = lastv;
+        }
+    }
+    int incl = lastv;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl = y > incl ? y : incl;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        const U x = __shfl_xor(mn, o), y = __shfl_xor(mx, o);
+        mn = x < mn ? x : mn;
+        mx = y > mx ? y : mx;
+    }
+    if (lane == kWave - 1) s_last[wave] = incl;
+    if (lane == 0) {
+        s_mn[wave] = mn;
+        s_mx[wave] = mx;
+    }
+    __syncthreads();
+    int in = __shfl_up(incl, 1);
+    if (lane == 0) in = 0;
+    for (int w = 0; w < wave; ++w) in = s_last[w] > in ? s_last[w] : in;
+    if (in == 0 && firstv != 0) s_first = firstv;  // the tile's first strict pair
+    int cnt = 0;
+    {
+        int pv = in;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if (d[r] != 0) {
+                if (pv != 0 && ((pv & 1) ? -1 : 1) == -d[r]) ++cnt;
+                pv = ((b0 + r + 1) << 1) | (d[r] < 0 ? 1 : 0);
+            }
+        }
+    }
+    int xc = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(xc, o);
+        if (lane >= o) xc += y;
+    }
+    if (lane == kWave - 1) s_cnt[wave] = xc;
+    __syncthreads();
+    int total = 0, hpre = xc - cnt;
+    for (int w = 0; w < NW; ++w) {
+        total += s_cnt[w];
+        if (w < wave) hpre += s_cnt[w];
+    }
+    if (total <= kRunHeads && cnt > 0) {
+        int pv = in;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if (d[r] != 0) {
+                if (pv != 0 && ((pv & 1) ? -1 : 1) == -d[r])
+                    out->heads[hpre++] = ((b0 + r) << 13) | (((pv >> 1) - 1) << 1) | (d[r] < 0 ? 1 : 0);
+                pv = ((b0 + r + 1) << 1) | (d[r] < 0 ? 1 : 0);
+            }
+        }
+    }
+    if (tid == 0) {
+        int lv = 0;
+        U tmn = s_mn[0], tmx = s_mx[0];
+        for (int w = 0; w < NW; ++w) {
+            lv = s_last[w] > lv ? s_last[w] : lv;
+            tmn = s_mn[w] < tmn ? s_mn[w] : tmn;
+            tmx = s_mx[w] > tmx ? s_mx[w] : tmx;
+        }
+        const int fv = s_first;
+        out->nh = total <= kRunHeads ? total : -1;
+        out->fz = fv > 0 ? (fv >> 1) - 1 : -1;
+        out->lz = lv > 0 ? (lv >> 1) - 1 : -1;
+        out->signs = (fv & 1) | ((lv & 1) << 1);
+        out->vmin = (unsigned long long)tmn;
+        out->vmax = (unsigned long long)tmx;
+    }
+}
+
+// Plan of the RUNS job (one workgroup of kVerWG threads).  ocost is the
+// remaining cost of the outlier job in pass-equivalents (huge if none);
+// was_runs: the probe chose RUNS, so a rejected plan falls back to GENERAL.
+// g = tile-sort tile / 4096 (1 or 2): a dense piece is the dense 4096-key
+// tiles of one tile-sort tile.  CH = outputs per merge chunk of the merge
+// launches; M = merge launches enqueued.
+template <class C>
+__device__ void run_plan(Ctl* ctl, int64_t n, int64_t ntiles, const typename C::S* keys, const RunTile* rd,
+                         RunArea* ra, int g, int64_t CH, int M, double ocost, bool was_runs) {
+    constexpr int NT = kVerWG;
+    constexpr int64_t TC = kClsTC;
+    __shared__ long long s_w[NT / kWave];
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    auto reject = [&]() {
+        if (tid == 0 && was_runs) ctl->path = SR_PATH_GENERAL;
+    };
+
+    // A. entries in array order: each tile's turnings -- the first one
+    //    against the last strict pair of earlier tiles (carried by a
+    //    max-scan) -- and the dense piece starts and ends; counted, then
+    //    written at the prefix offset.  Tiles in contiguous ranges per thread.
+    const int64_t per = (ntiles + NT - 1) / NT;
+    const int64_t t0 = (int64_t)tid * per < ntiles ? (int64_t)tid * per : ntiles;
+    const int64_t t1 = (t0 + per) < ntiles ? (t0 + per) : ntiles;
+    auto lastv = [&](int64_t t) {  // ((index + 1) << 1 | descending) of tile t's last strict pair
+        const RunTile& r = rd[t];
+        return r.lz < 0 ? 0LL : ((((long long)(t * TC + r.lz)) + 1) << 1) | ((r.signs >> 1) & 1);
+    };
+    long long agg = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const long long v = lastv(t);
+        agg = v > agg ? v : agg;
+    }
+    long long incl = agg;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const long long y = __shfl_up(incl, o);
+        if (lane >= o) incl = y > incl ? y : incl;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    long long carry = __shfl_up(incl, 1);
+    if (lane == 0) carry = 0;
+    for (int w = 0; w < wave; ++w) carry = s_w[w] > carry ? s_w[w] : carry;
+
+    long long cnt = 0, dense_keys = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        long long o = 0;
+        if (pass == 1) {
+            long long tot, dk;
+            o = wg_scan_excl(cnt, s_w, tot);
+            (void)wg_scan_excl(dense_keys, s_w, dk);
+            if (tot + 1 > kRunMaxBase || 2 * dk > n) {  // leaves = boundaries + 1
+                reject();
+                return;
+            }
+            if (tid == 0) ra->nbase = tot;  // entries, for now
+            dense_keys = dk;
+        }
+        auto put = [&](long long pos, long long kind, long long j) {
+            if (pass) {
+                ra->ent[o] = pos | (kind << 56);
+                ra->ent_j[o] = j;
+                ++o;
+            } else {
+                ++cnt;
+            }
+        };
+        long long c = carry;
+        for (int64_t t = t0; t < t1; ++t) {
+            const RunTile& r = rd[t];
+            const int nh = r.nh, fz = r.fz;
+            const bool pdense = t > 0 && rd[t - 1].nh < 0;
+            const int64_t s = t * TC;
+            if (nh < 0) {
+                if (t > 0 && ((t % g) == 0 || !pdense)) put(s, 2, 0);
+                if (!pass) dense_keys += ((s + TC) < n ? (s + TC) : n) - s;
+            } else {
+                if (pdense) put(s, 3, 0);
+                if (fz >= 0 && c != 0) {
+                    const int cs = (c & 1) ? -1 : 1, fs = (r.signs & 1) ? -1 : 1;
+                    if (cs == -fs) put(s + fz, fs < 0 ? 5 : 4, (c >> 1) - 1);
+                }
+                for (int h = 0; h < nh; ++h) {
+                    const int v = r.heads[h];
+                    put(s + (v >> 13), (v & 1) ? 5 : 4, s + ((v >> 1) & 0xFFF));
+                }
+            }
+            const long long v = lastv(t);
+            if (v != 0) c = v;
+        }
+    }
+    __syncthreads();
+
+    // B. leaf boundaries: dense markers, and the boundary of each turning
+    //    (valley 4 at i+1 unless the descending stretch before it is a single
+    //    pair, then j+1; peak 5 at j+1 unless the descending stretch after it
+    //    is a single pair, then i+1), once per position; a turning whose
+    //    boundary falls on or inside an adjacent dense piece adds none.
+    {
+        const long long ne = ra->nbase;
+        auto tpos = [&](long long m) -> long long {
+            const long long e = ra->ent[m];
+            const long long i = bpos(e), j = ra->ent_j[m];
+            long long p;
+            if (bkind(e) == 5) {
+                const bool single = m + 1 < ne && bkind(ra->ent[m + 1]) >= 4 && ra->ent_j[m + 1] == i;
+                p = single ? i + 1 : j + 1;
+            } else {
+                const bool single = m > 0 && bkind(ra->ent[m - 1]) >= 4 && bpos(ra->ent[m - 1]) == j;
+                p = single ? j + 1 : i + 1;
+            }
+            if (m > 0 && bkind(ra->ent[m - 1]) == 3 && p <= bpos(ra->ent[m - 1])) return -1;
+            if (m + 1 < ne && bkind(ra->ent[m + 1]) == 2 && p >= bpos(ra->ent[m + 1])) return -1;
+            return p;
+        };
+        auto boundary = [&](long long m) -> long long {  // packed boundary, or -1
+            const long long e = ra->ent[m];
+            if (bkind(e) < 4) return e;
+            const long long p = tpos(m);
+            if (p < 0) return -1;
+            if (m > 0 && bkind(ra->ent[m - 1]) >= 4 && tpos(m - 1) == p) return -1;
+            return p | (1LL << 56);
+        };
+        const long long pb = (ne + NT - 1) / NT;
+        const long long i0 = (long long)tid * pb < ne ? (long long)tid * pb : ne;
+        const long long i1 = (i0 + pb) < ne ? (i0 + pb) : ne;
+        long long k = 0;
+        for (long long m = i0; m < i1; ++m) k += boundary(m) >= 0 ? 1 : 0;
+        long long tot;
+        long long o = 1 + wg_scan_excl(k, s_w, tot);
+        for (long long m = i0; m < i1; ++m) {
+            const long long b = boundary(m);
+            if (b >= 0) ra->bs[o++] = b;
+        }
+        if (tid == 0) {
+            ra->bs[0] = (long long)(rd[0].nh < 0 ? 2 : 0) << 56;
+            ra->bs[tot + 1] = n;
+            ra->nbase = tot + 1;
+        }
+    }
+    __syncthreads();
+
+    // C. extremes of every leaf, descending runs and their reversal units
+    const long long nl = ra->nbase;
+    const long long pl = (nl + NT - 1) / NT;
+    const long long l0 = (long long)tid * pl < nl ? (long long)tid * pl : nl;
+    const long long l1 = (l0 + pl) < nl ? (l0 + pl) : nl;
+    long long desc_keys = 0;
+    {
+        long long nd = 0, units = 0;
+        for (long long i = l0; i < l1; ++i) {
+            const long long b = ra->bs[i];
+            const long long s = bpos(b), e = bpos(ra->bs[i + 1]);
+            unsigned long long mn = ~0ull, mx = 0ull;
+            if (bkind(b) == 2) {
+                for (long long t = s / TC; t * TC < e; ++t) {
+                    mn = rd[t].vmin < mn ? rd[t].vmin : mn;
+                    mx = rd[t].vmax > mx ? rd[t].vmax : mx;
+                }
+            } else if (e > s) {
+                const unsigned long long a = (unsigned long long)C::enc(keys[s]);
+                const unsigned long long z = (unsigned long long)C::enc(keys[e - 1]);
+                mn = a < z ? a : z;
+                mx = a < z ? z : a;
+                if (a > z) {
+                    ++nd;
+                    units += ((e - s) / 2 + kRevPairs - 1) / kRevPairs;
+                    desc_keys += e - s;
+                }
+            }
+            ra->bmin[i] = mn;
+            ra->bmax[i] = mx;
+        }
+        long long tnd, tun, tdk;
+        long long od = wg_scan_excl(nd, s_w, tnd);
+        long long ou = wg_scan_excl(units, s_w, tun);
+        (void)wg_scan_excl(desc_keys, s_w, tdk);
+        desc_keys = tdk;
+        for (long long i = l0; i < l1; ++i) {
+            const long long b = ra->bs[i];
+            if (bkind(b) == 2) continue;
+            const long long s = bpos(b), e = bpos(ra->bs[i + 1]);
+            if (e <= s) continue;
+            const unsigned long long a = (unsigned long long)C::enc(keys[s]);
+            const unsigned long long z = (unsigned long long)C::enc(keys[e - 1]);
+            if (a > z) {
+                ra->ds[od] = s;
+                ra->de[od] = e;
+                ra->dpre[od] = ou;
+                ++od;
+                ou += ((e - s) / 2 + kRevPairs - 1) / kRevPairs;
+            }
+        }
+        if (tid == 0) {
+            ra->ndesc = tnd;
+            ra->nrev = tun;
+            ra->dpre[tnd] = tun;
+        }
+    }
+    __syncthreads();
+
+    // D. in-order joins: leaf i continues leaf i-1 when max(i-1) <= min(i)
+    {
+        auto starts = [&](long long i) { return i == 0 || ra->bmax[i - 1] > ra->bmin[i]; };
+        long long k = 0;
+        for (long long i = l0; i < l1; ++i) k += starts(i) ? 1 : 0;
+        long long L;
+        long long o = wg_scan_excl(k, s_w, L);
+        if (L > kRunMaxLeaves) {
+            reject();
+            return;
+        }
+        for (long long i = l0; i < l1; ++i)
+            if (starts(i)) ra->lb[o++] = bpos(ra->bs[i]);
+        if (tid == 0) {
+            ra->lb[L] = n;
+            ra->L = L;
+        }
+    }
+    __syncthreads();
+    const long long L = ra->L;
+    const int P = ceil_log2_dev(L);
+    const int np = P + (P & 1);
+    const double rcost = (double)(desc_keys + dense_keys) / (double)n + np;
+    const double gcost = 1.0 + M;
+    if (np > M || !(rcost < gcost) || !(rcost < ocost)) {
+        reject();
+        return;
+    }
+
+    // E. chunk prefixes of every pass: pass k merges groups of 2^(k+1)
+    //    leaves (first half with second half); at k = P (odd P) one group
+    //    holds every leaf as its first half: a copy back into U
+    long long base = 0;
+    for (int k = 0; k < np; ++k) {
+        const long long G = (L + (2LL << k) - 1) >> (k + 1);
+        long long ch = 0;
+        if (tid < G) {
+            const long long a = (long long)tid << (k + 1);
+            const long long z = (a + (2LL << k)) < L ? (a + (2LL << k)) : L;
+            ch = (ra->lb[z] - ra->lb[a] + CH - 1) / CH;
+        }
+        long long tot;
+        const long long pre = wg_scan_excl(ch, s_w, tot);
+        if (tid < G) ra->pre[base + tid] = pre;
+        if (tid == 0) {
+            ra->pre[base + G] = tot;
+            ra->pbase[k] = base;
+            ra->ptotal[k] = tot;
+        }
+        base += G + 1;
+    }
+    if (tid == 0) {
+        ra->npasses = np;
+        ra->P = P;
+        ctl->path = SR_PATH_RUNS;
+        ctl->run[0] = (unsigned long long)L;
+        ctl->run[1] = (unsigned long long)np;
+        ctl->run[2] = (unsigned long long)desc_keys;
+        ctl->run[3] = (unsigned long long)dense_keys;
+    }
+}
+
+// Reversal units of the descending runs (scatter launch, 256 threads):
+// unit j of run [s, e) swaps the pairs (s+p, e-1-p) for p in
+// [j*kRevPairs, (j+1)*kRevPairs) below (e-s)/2, every load before any store.
+template <class S>
+__device__ void runs_reverse(S* keys, const RunArea* ra) {
+    const long long nrev = ra->nrev, nd = ra->ndesc;
+    for (long long u = blockIdx.x; u < nrev; u += gridDim.x) {
+        long long lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (ra->dpre[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const long long s = ra->ds[lo], e = ra->de[lo];
+        const long long half = (e - s) / 2;
+        const long long p0 = (u - ra->dpre[lo]) * kRevPairs;
+        S a[kRevPer], b[kRevPer];
+#pragma unroll
+        for (int r = 0; r < kRevPer; ++r) {
+            const long long p = p0 + threadIdx.x + r * kClsWG;
+            if (p < half && p < p0 + kRevPairs) {
+                a[r] = keys[s + p];
+                b[r] = keys[e - 1 - p];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRevPer; ++r) {
+            const long long p = p0 + threadIdx.x + r * kClsWG;
+            if (p < half && p < p0 + kRevPairs) {
+                keys[s + p] = b[r];
+                keys[e - 1 - p] = a[r];
+            }
+        }
+    }
+}
+
+// Merge pass k of the RUNS job: chunks of the pass's groups, grid-stride.
+template <class MC, class S>
+__device__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, int k) {
+    if (k >= ra->npasses) return;
+    const long long total = ra->ptotal[k];
+    const long long* pre = ra->pre + ra->pbase[k];
+    const long long L = ra->L;
+    const long long G = (L + (2LL << k) - 1) >> (k + 1);
+    const S* src = (k & 1) ? S1 : U;
+    S* dst = (k & 1) ? U : S1;
+    for (long long c = blockIdx.x; c < total; c += gridDim.x) {
+        long long lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const long long l0 = lo << (k + 1);
+        const long long lm = (l0 + (1LL << k)) < L ? (l0 + (1LL << k)) : L;
+        const long long le = (l0 + (2LL << k)) < L ? (l0 + (2LL << k)) : L;
+        const long long a0 = ra->lb[l0], mid = ra->lb[lm], e = ra->lb[le];
+        MC::run(sm, src + a0, dst + a0, nullptr, nullptr, e - a0, e - a0, mid - a0, (c - pre[lo]) * MC::CH,
+                nullptr);
+        __syncthreads();
+    }
+}
+
+
 // ============================================================== kernels
 
 // Tile-sort launch.  GENERAL / OUTLIER: the tile sort of the job's array
@@ -71,9 +643,47 @@ __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
 // [b*T/2, (b+1)*T/2) of [0, n/2), in place in U.
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::S* S1, uint32_t* PU,
-                                                  uint32_t* PS1, int64_t n, int M, const Ctl* ctl) {
+                                                  uint32_t* PS1, int64_t n, int M, const Ctl* ctl,
+                                                  const RunTile* rdesc) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
+    if constexpr (!PAIRS) {
+        // RUNS: sort the dense 4096-key tiles of this tile in place, both at
+        // once when both are dense (the plan's dense pieces)
+        if (ctl != nullptr && rdesc != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
+            constexpr int G = TS::T / kClsTC;
+            static_assert(G == 1 || G == 2, "tile = 1 or 2 run-scan tiles");
+            __shared__ typename TS::Smem sm;
+            const int64_t ncls = (n + kClsTC - 1) / kClsTC;
+            const int64_t q0 = (int64_t)blockIdx.x * G;
+            const bool d0 = q0 < ncls && rdesc[q0].nh < 0;
+            const bool d1 = G == 2 && q0 + 1 < ncls && rdesc[q0 + 1].nh < 0;
+            int64_t s0 = -1, e0 = -1, s1 = -1, e1 = -1;
+            if (d0 && d1) {
+                s0 = q0 * kClsTC;
+                e0 = (q0 + 2) * kClsTC;
+            } else {
+                if (d0) {
+                    s0 = q0 * kClsTC;
+                    e0 = s0 + kClsTC;
+                }
+                if (d1) {
+                    s1 = (q0 + 1) * kClsTC;
+                    e1 = s1 + kClsTC;
+                }
+            }
+            if (s0 >= 0) {
+                e0 = e0 < n ? e0 : n;
+                TS::run(sm, U + s0, U + s0, nullptr, nullptr, (int)(e0 - s0));
+            }
+            if (s1 >= 0) {
+                e1 = e1 < n ? e1 : n;
+                __syncthreads();
+                TS::run(sm, U + s1, U + s1, nullptr, nullptr, (int)(e1 - s1));
+            }
+            return;
+        }
+    }
     if (ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_REVERSED) {
         constexpr int H = TS::T / 2;
         constexpr int R = H / WG;
@@ -145,28 +755,46 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
 // Merge slot k, one chunk per workgroup, co-ranks searched in the workgroup.
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
-                                              int64_t n, int M, int64_t T, int k, const Ctl* ctl) {
+                                              int64_t n, int M, int64_t T, int k, const Ctl* ctl,
+                                              const RunArea* ra) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     using S = typename C::S;
+    __shared__ typename MC::Smem sm;
+    if constexpr (!PAIRS) {
+        if (ra != nullptr && ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
+            runs_merge<MC, S>(sm, ra, U, S1, k);
+            return;
+        }
+    }
     const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
     if (!v.active) return;
     const int64_t out0 = (int64_t)blockIdx.x * MC::CH;
     if (out0 >= v.n) return;
-    __shared__ typename MC::Smem sm;
     MC::run(sm, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, out0, nullptr);
 }
 
 // Merge slot k, persistent double-buffered, co-ranks from k_partition.
+// RUNS passes reuse its LDS for one-chunk merges with in-kernel co-ranks.
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
-                                                      const int64_t* co, const Ctl* ctl) {
+                                                      const int64_t* co, const Ctl* ctl, const RunArea* ra) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
+    using MC = typename MP::MC;
     using S = typename C::S;
+    __shared__ union {
+        typename MP::Smem p;
+        typename MC::Smem c;
+    } sm;
+    if constexpr (!PAIRS) {
+        if (ra != nullptr && ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
+            runs_merge<MC, S>(sm.c, ra, U, S1, k);
+            return;
+        }
+    }
     const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
     if (!v.active) return;
-    __shared__ typename MP::Smem sm;
-    MP::run(sm, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
+    MP::run(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
 }
 
 // --------------------------------------------------------------- outliers
@@ -186,25 +814,15 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
 //               m <= n/2, else GENERAL -- U is still untouched).
 //   k_scatter   kept keys to S1[0, n-m) in input order, outliers to
 //               S1[n-m, n) (from the end backwards).
-constexpr int kClsWG = 256;
-constexpr int kClsPer = 17;
-constexpr int kClsW = kClsWG * kClsPer;  // 4352-key window
-constexpr int kClsTC = 4096;             // core keys per tile
-constexpr int kClsH = (kClsW - kClsTC) / 2;
-constexpr int kClsMaxIter = 48;
-
-__device__ __forceinline__ int ceil_log2_dev(int64_t x) {
-    int r = 0;
-    while (((int64_t)1 << r) < x) ++r;
-    return r;
-}
-
 template <class C>
 __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, int64_t n, Ctl* ctl,
                                                      unsigned int* flags, unsigned long long* tfirst,
-                                                     unsigned long long* tlast, unsigned long long* tcount) {
+                                                     unsigned long long* tlast, unsigned long long* tcount,
+                                                     int runs_ok, RunTile* rdesc) {
     using U = typename C::U;
-    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+    const int path = ld_agent(&ctl->path);
+    const bool do_runs = runs_ok && (path == SR_PATH_RUNS || path == SR_PATH_OUTLIER);
+    if (path != SR_PATH_OUTLIER && !do_runs) return;
     __shared__ U sk[kClsW];
     __shared__ uint16_t dx[kClsW];  // dense list of kept keys: window index of the q-th kept key
     __shared__ uint8_t kp[kClsW];
@@ -240,6 +858,8 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
         }
     }
     __syncthreads();
+    if (do_runs) runscan_lds<U>(sk, n, c0, c1, w0, rdesc + t);
+    if (path != SR_PATH_OUTLIER) return;
 
     bool converged = false;
     const int bj = tid * kClsPer;
@@ -400,15 +1020,21 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
 // assigned striped (key e of the tile to thread e mod 256), so loads and the
 // mostly consecutive kept stores coalesce; a key's kept rank is the popcount
 // prefix of the tile's mask words (scanned in LDS) plus the bits below it.
+// The same launch reverses the descending runs of the RUNS job.
 template <class C>
-__global__ __launch_bounds__(kClsWG) void k_scatter(const typename C::S* keys, int64_t n, const Ctl* ctl,
+__global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t n, const Ctl* ctl,
                                                     typename C::S* s1, const unsigned int* flags,
-                                                    const unsigned long long* kpref_t) {
+                                                    const unsigned long long* kpref_t, const RunArea* ra) {
     using S = typename C::S;
     constexpr int CP = kClsTC / kClsWG;
     constexpr int NW = kClsTC / 32;  // mask words per tile
     static_assert(NW <= kClsWG, "one word per thread in the scan");
-    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+    const int path = ld_agent(&ctl->path);
+    if (path == SR_PATH_RUNS && ra != nullptr) {
+        runs_reverse<S>(keys, ra);
+        return;
+    }
+    if (path != SR_PATH_OUTLIER) return;
     __shared__ unsigned int sw[NW];
     __shared__ int spre[NW];
     __shared__ int wtot[kClsWG / kWave];
@@ -461,12 +1087,34 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(const typename C::S* keys, i
 // at least the last kept key of the nearest earlier tile that kept any.
 // Then the job is OUTLIER with m = n - kept outliers when m <= n/2;
 // otherwise GENERAL (the user buffer has not been written yet).
-constexpr int kVerWG = 1024;
+//
+// With runs_ok the same workgroup then plans the RUNS job (run_plan) when the
+// probe chose RUNS, or beside an OUTLIER job (unless OUTLIER was forced); the
+// cheaper of the two is kept.
+__device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
+                                const unsigned long long* tlast, const unsigned long long* tcount,
+                                unsigned long long* kpref_t, int64_t T_sort, double* ocost);
 
+template <class C>
 __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
                                                    const unsigned long long* tlast, const unsigned long long* tcount,
-                                                   unsigned long long* kpref_t, int64_t T_sort) {
-    if (ld_agent(&ctl->path) != SR_PATH_OUTLIER) return;
+                                                   unsigned long long* kpref_t, int64_t T_sort,
+                                                   const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
+                                                   int runs_ok, int64_t merge_ch, int M) {
+    const int path0 = ld_agent(&ctl->path);
+    const bool want_runs =
+        runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->force_path != SR_PATH_OUTLIER));
+    __shared__ double s_ocost;
+    if (path0 == SR_PATH_OUTLIER) verify_outliers(ctl, n, ntiles, tfirst, tlast, tcount, kpref_t, T_sort, &s_ocost);
+    else if (path0 == SR_PATH_RUNS && threadIdx.x == 0) s_ocost = 1e300;
+    __syncthreads();
+    if (want_runs) run_plan<C>(ctl, n, ntiles, keys, rdesc, ra, (int)(T_sort / kClsTC), merge_ch, M, s_ocost,
+                               path0 == SR_PATH_RUNS);
+}
+
+__device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
+                                const unsigned long long* tlast, const unsigned long long* tcount,
+                                unsigned long long* kpref_t, int64_t T_sort, double* ocost) {
     __shared__ unsigned long long s_last[kVerWG];
     __shared__ int s_has[kVerWG];
     __shared__ unsigned long long s_kept[kVerWG / kWave];
@@ -547,9 +1195,13 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
             ctl->path = SR_PATH_GENERAL;
             ctl->m = 0;
             ctl->job_passes = 0;
+            *ocost = 1e300;
         } else {
+            const int jp = ceil_log2_dev((m + T_sort - 1) / T_sort);
             ctl->m = (unsigned long long)m;
-            ctl->job_passes = ceil_log2_dev((m + T_sort - 1) / T_sort);
+            ctl->job_passes = jp;
+            // scatter (1) + outlier sort (1 + jp passes over m) + final merge (1)
+            *ocost = 2.0 + (1.0 + jp) * (double)m / (double)n;
         }
         ctl->n_kept = total;
         ctl->reserved[2] = fail ? 1 : 0;
@@ -568,7 +1220,7 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
 // finish turns the counters into the plan and clears them.
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
-                                                    unsigned long long* slots, int outlier_ok) {
+                                                    unsigned long long* slots, int jobs_ok) {
     using U = typename C::U;
     using S = typename C::S;
     constexpr int VN = 16 / sizeof(S);
@@ -582,6 +1234,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     const int64_t ntiles = (npairs + kProbeTile - 1) / kProbeTile;
 
     // sample: kProbeSample pairs at the start of tile blockIdx * ntiles / gridDim
+    // sd: sampled descents (low 32 bits) and turning points, where two strict
+    // neighbouring pairs point different ways (high 32 bits)
     unsigned long long sd = 0, sp = 0;
     {
         const int64_t t = (int64_t)blockIdx.x * ntiles / gridDim.x;
@@ -591,6 +1245,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
             sd += x > y ? 1 : 0;
             sp += 1;
+            if (i + 1 < npairs) {
+                const U z = C::enc(keys[i + 2]);
+                if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << 32;
+            }
         }
     }
     unsigned long long d = 0, a = 0;
@@ -702,16 +1360,20 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             for (int q = 0; q < 4; ++q) tot[q] += red[q][w];
         const unsigned long long desc = tot[0];
         const unsigned long long asc = tot[1];
-        const unsigned long long sdesc = tot[2];
+        const unsigned long long sdesc = tot[2] & 0xFFFFFFFFull;
+        const unsigned long long sturn = tot[2] >> 32;
         const unsigned long long spairs = tot[3];
         const bool mixed = ld_agent(&ctl->mixed) != 0;
+        const bool outlier_ok = (jobs_ok & 1) != 0, runs_ok = (jobs_ok & 2) != 0;
         int path;
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
         else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
         else if (outlier_ok && sdesc * 16 <= spairs) path = SR_PATH_OUTLIER;
+        else if (runs_ok && sturn * 64 <= spairs) path = SR_PATH_RUNS;
         else path = SR_PATH_GENERAL;
         const int force = ctl->force_path;
-        if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok)) path = force;
+        if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok) || (force == SR_PATH_RUNS && runs_ok))
+            path = force;
         ctl->path = path;
         ctl->reserved[0] = desc;   // kept for sr_last_stats
         ctl->reserved[1] = asc;
@@ -1024,7 +1686,8 @@ std::mutex g_mu;
 int g_force_path = -1;
 bool g_profile = false;
 int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
-bool g_outlier_enabled = true;                   // allow the OUTLIER path for keys-only sorts
+bool g_outlier_enabled = true;
+bool g_runs_enabled = true;                      // allow the RUNS path for keys-only sorts                   // allow the OUTLIER path for keys-only sorts
 int g_tile_variant = -1;  // -1 auto (1024 x 8 below partition_min_n), 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
 int g_merge_items = 8;    // fused merge: outputs per thread (16 or 8, 32-bit keys only)
 
@@ -1251,7 +1914,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         // One tile: sort in place, no probe.
         ProfScope ps(ls, "tile_sort");
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, ls, keys, keys,
-                           pay, pay, n, 0, (const Ctl*)nullptr);
+                           pay, pay, n, 0, (const Ctl*)nullptr, (const RunTile*)nullptr);
         SR_LAUNCH_CHECK("tile_sort");
         lc.trivial = 1;
         std::lock_guard<std::mutex> lk(g_mu);
@@ -1260,14 +1923,20 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     }
     const int64_t nchunks = cdiv(n, CH);
     const bool outlier_ok = !PAIRS && g_outlier_enabled;
-    const int64_t ncls = outlier_ok ? cdiv(n, kClsTC) : 0;
+    const bool runs_ok = !PAIRS && g_runs_enabled;
+    const bool scan_ok = outlier_ok || runs_ok;
+    const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
     const size_t co_bytes = round_up((size_t)(nchunks + 2) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
     const size_t cls_arr = round_up((size_t)ncls * 8, 256);
     Workspace* ws = nullptr;
     // aux: tile offsets, first/last kept keys, kept counts, kept bit masks
     const size_t flag_bytes = round_up((size_t)ncls * (kClsTC / 8), 256);
-    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws, 4 * cls_arr + flag_bytes);
+    // run descriptors and the run plan
+    const size_t rdesc_bytes = runs_ok ? round_up((size_t)ncls * sizeof(RunTile), 256) : 0;
+    const size_t rarea_bytes = runs_ok ? round_up(sizeof(RunArea), 256) : 0;
+    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws,
+                                4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes);
     if (s != SR_OK || prepare_only) return s;
     Ctl* ctl = ws->ctl;
     char* wd = static_cast<char*>(ws_data(ws));
@@ -1275,37 +1944,46 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     S* skeys = reinterpret_cast<S*>(wd + co_bytes);
     uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes) : nullptr;
     const bool use_partition = n >= g_partition_min_n;
+    const bool merge8 = sizeof(S) == 4 && !PAIRS && TN::MIT == 16 && g_merge_items == 8;
+    const int64_t merge_ch = use_partition ? CH : (merge8 ? (int64_t)TN::MWG * 8 : CH);
+    RunTile* rdesc = nullptr;
+    RunArea* rarea = nullptr;
 
     {
         ProfScope ps(ls, "probe");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
         hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
-                           outlier_ok ? 1 : 0);
+                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0));
         SR_LAUNCH_CHECK("probe");
     }
-    if (outlier_ok) {
+    if (scan_ok) {
         unsigned long long* aux = static_cast<unsigned long long*>(ws->aux);
         unsigned long long* kpref_t = aux;
         unsigned long long* tfirst = aux + cls_arr / 8;
         unsigned long long* tlast = aux + 2 * (cls_arr / 8);
         unsigned long long* tcount = aux + 3 * (cls_arr / 8);
         unsigned int* flags = reinterpret_cast<unsigned int*>(aux + 4 * (cls_arr / 8));
+        if (runs_ok) {
+            rdesc = reinterpret_cast<RunTile*>(reinterpret_cast<char*>(flags) + flag_bytes);
+            rarea = reinterpret_cast<RunArea*>(reinterpret_cast<char*>(rdesc) + rdesc_bytes);
+        }
         {
             ProfScope ps(ls, "classify");
             hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n, ctl,
-                               flags, tfirst, tlast, tcount);
+                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc);
             SR_LAUNCH_CHECK("classify");
         }
         {
             ProfScope ps(ls, "verify");
-            hipLaunchKernelGGL(k_verify, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
+            hipLaunchKernelGGL(k_verify<C>, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
-                               (const unsigned long long*)tcount, kpref_t, (int64_t)T);
+                               (const unsigned long long*)tcount, kpref_t, (int64_t)T, (const S*)keys,
+                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M);
             SR_LAUNCH_CHECK("verify");
         }
         ProfScope ps(ls, "scatter");
-        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n,
-                           (const Ctl*)ctl, skeys, (const unsigned int*)flags, (const unsigned long long*)kpref_t);
+        hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, keys, n, (const Ctl*)ctl, skeys,
+                           (const unsigned int*)flags, (const unsigned long long*)kpref_t, (const RunArea*)rarea);
         SR_LAUNCH_CHECK("scatter");
     }
     {
@@ -1314,13 +1992,13 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
             if (g_tile_variant == 1 || (g_tile_variant == -1 && !use_partition)) {
                 hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
-                                   skeys, pay, spay, n, M, (const Ctl*)ctl);
+                                   skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc);
                 SR_LAUNCH_CHECK("tile_sort");
                 goto tile_done;
             }
         }
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, ls,
-                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl);
+                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc);
         SR_LAUNCH_CHECK("tile_sort");
     }
 tile_done:
@@ -1343,22 +2021,23 @@ tile_done:
             auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
-                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl);
+                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea);
             SR_LAUNCH_CHECK("merge");
         } else {
             ProfScope ps(ls, "merge");
             bool done = false;
             if constexpr (sizeof(S) == 4 && !PAIRS && TN::MIT == 16) {
-                if (g_merge_items == 8) {
+                if (merge8) {
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)cdiv(n, TN::MWG * 8)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
-                                       (const Ctl*)ctl);
+                                       (const Ctl*)ctl, (const RunArea*)rarea);
                     done = true;
                 }
             }
             if (!done)
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0,
-                                   ls, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl);
+                                   ls, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl,
+                                   (const RunArea*)rarea);
             SR_LAUNCH_CHECK("merge");
         }
     }
@@ -1788,12 +2467,23 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
         case SR_PATH_OUTLIER: {
             const double m = (double)h.m;
             out->outliers = (int64_t)h.m;
+            out->merge_passes = h.job_passes + 1;
             // classify (n read, n written) + outlier sort (tile + P merges on m)
             // + final merge of kept and outliers (n read, n written)
             eq = 2.0 + (1.0 + h.job_passes) * m / (double)lc.n;
             break;
         }
-        default: eq = 1 + lc.merge_passes; break;
+        case SR_PATH_RUNS: {
+            // run scan (n read) + reversal and dense tile sorts + merge tree
+            out->run_leaves = (int64_t)h.run[0];
+            out->merge_passes = (int32_t)h.run[1];
+            eq = 0.5 + (double)(h.run[2] + h.run[3]) / (double)lc.n + (double)h.run[1];
+            break;
+        }
+        default:
+            out->merge_passes = lc.merge_passes;
+            eq = 1 + lc.merge_passes;
+            break;
         }
         out->passes = (int32_t)std::ceil(eq - 1e-9);
         out->bytes_moved = eq * 2.0 * (double)lc.n * (double)lc.es;
@@ -1822,7 +2512,7 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (!name) return fail(SR_ERR_INVALID_ARGUMENT, "name is NULL");
     std::lock_guard<std::mutex> lk(g_mu);
     if (std::strcmp(name, "force_path") == 0) {
-        if (value < -1 || value > SR_PATH_GENERAL) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
+        if (value < -1 || value > SR_PATH_RUNS) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
         g_force_path = (int)value;
         return SR_OK;
     }
@@ -1849,6 +2539,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "outlier_path") == 0) {
         if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "outlier_path is 0 or 1");
         g_outlier_enabled = value != 0;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "runs_path") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "runs_path is 0 or 1");
+        g_runs_enabled = value != 0;
         return SR_OK;
     }
     if (std::strcmp(name, "profile") == 0) {

@@ -22,6 +22,8 @@ plus the batched / key-value / serving mixes):
                 one of the four types above
   normal_f32    standard normal float32 with 1% repeated values, signed zeros
                 and NaNs of both signs (IEEE totalOrder matters)
+  k-classes     the presorted classes of Sec. 2: k-equal, k-even, k-sharp and
+                k-shuffled teeth, k-distance, k-exchange, k-limited
 """
 from __future__ import annotations
 
@@ -137,6 +139,128 @@ def int32_of_type(kind: str, n: int, seed: int) -> np.ndarray:
     if kind == "few":
         return few_unique_int32(n, seed)
     raise ValueError(kind)
+
+
+# ------------------------------------------- the k-classes of Sec. 2 (int32)
+# Built from their definitions on 1..n without the "blow-up" maps, which are
+# strictly increasing and so change no comparison between two keys.  Section
+# i of k holds floor((i+1)n/k) - floor(i n/k) positions (equal sections when
+# k divides n).  "Odd numbered" sections are the first, third, ... (index
+# 0, 2, ... here).
+
+CLASSES = ("equal_teeth", "even_teeth", "sharp_teeth", "shuffled_teeth", "distance", "exchange", "limited")
+
+
+def _sections(n: int, k: int) -> np.ndarray:
+    return (np.arange(k + 1, dtype=np.int64) * n) // k
+
+
+def equal_teeth(n: int, k: int) -> np.ndarray:
+    """k sections, each ascending 1 .. its length."""
+    b = _sections(n, k)
+    pos = np.arange(n, dtype=np.int64)
+    sec = np.searchsorted(b, pos, side="right") - 1
+    return (pos - b[sec] + 1).astype(np.int32)
+
+
+def even_teeth(n: int, k: int) -> np.ndarray:
+    """k-equal teeth with every odd-numbered section reversed (k = 2: organ pipe
+    from the descending side; k = 1: reversed)."""
+    b = _sections(n, k)
+    pos = np.arange(n, dtype=np.int64)
+    sec = np.searchsorted(b, pos, side="right") - 1
+    up = pos - b[sec] + 1
+    down = b[sec + 1] - pos
+    return np.where(sec % 2 == 0, down, up).astype(np.int32)
+
+
+def sharp_teeth(n: int, k: int) -> np.ndarray:
+    """1..n in k sections, odd-numbered sections reversed (k = 1: reversed)."""
+    b = _sections(n, k)
+    pos = np.arange(n, dtype=np.int64)
+    sec = np.searchsorted(b, pos, side="right") - 1
+    mirrored = b[sec] + b[sec + 1] - 1 - pos
+    return (np.where(sec % 2 == 0, mirrored, pos) + 1).astype(np.int32)
+
+
+def shuffled_teeth(n: int, k: int, seed: int) -> np.ndarray:
+    """The k sections of a k-sharp teeth list interleaved at random, each
+    section keeping its own order (a uniformly random interleaving: a
+    Fisher-Yates shuffle of the section labels)."""
+    a = sharp_teeth(n, k)
+    b = _sections(n, k)
+    labels = np.repeat(np.arange(k, dtype=np.int64), np.diff(b))
+    r = stream(seed, n)
+    for i in range(n - 1, 0, -1):
+        j = int(below(r[i:i + 1], i + 1)[0])
+        labels[i], labels[j] = labels[j], labels[i]
+    out = np.empty(n, dtype=np.int32)
+    for s in range(k):
+        out[labels == s] = a[b[s]:b[s + 1]]
+    return out
+
+
+def distance(n: int, k: int, seed: int) -> np.ndarray:
+    """1..n cut into sections of k+1 keys (the last may be shorter), each
+    shuffled (Fisher-Yates, all sections at once); every key ends within k of
+    its rank."""
+    a = np.arange(1, n + 1, dtype=np.int64)
+    w = k + 1
+    full = (n // w) * w
+    blk = a[:full].reshape(-1, w) if full else a[:0].reshape(0, w)
+    r = stream(seed, max(1, w * max(1, blk.shape[0])))
+    for j in range(w - 1, 0, -1):
+        if blk.shape[0] == 0:
+            break
+        pick = below(r[j * blk.shape[0]:(j + 1) * blk.shape[0]], j + 1).astype(np.int64)
+        rows = np.arange(blk.shape[0])
+        t = blk[rows, j].copy()
+        blk[rows, j] = blk[rows, pick]
+        blk[rows, pick] = t
+    tail = a[full:]
+    rt = stream(seed ^ 0x7A11, max(1, tail.size))
+    for j in range(tail.size - 1, 0, -1):
+        q = int(below(rt[j:j + 1], j + 1)[0])
+        tail[j], tail[q] = tail[q], tail[j]
+    return np.concatenate([blk.reshape(-1), tail]).astype(np.int32)
+
+
+def exchange(n: int, k: int, seed: int) -> np.ndarray:
+    """1..n, then k exchanges of two uniformly drawn positions."""
+    a = np.arange(1, n + 1, dtype=np.int64)
+    if n > 0:
+        pq = below(stream(seed, 2 * k), n).astype(np.int64)
+        for p, q in zip(pq[0::2], pq[1::2]):
+            a[p], a[q] = a[q], a[p]
+    return a.astype(np.int32)
+
+
+def limited(n: int, k: int, seed: int) -> np.ndarray:
+    """At most 2^k distinct values: uniform k-bit integers; k = 0 gives all
+    zeros, k >= 32 the full int32 range (random integers, as Sec. 2 notes)."""
+    if k == 0:
+        return np.zeros(n, dtype=np.int32)
+    if k >= 32:
+        return random_int32(n, seed)
+    return below(stream(seed, n), 1 << k).astype(np.int64).astype(np.int32)
+
+
+def class_int32(name: str, n: int, k: int, seed: int) -> np.ndarray:
+    if name == "equal_teeth":
+        return equal_teeth(n, k)
+    if name == "even_teeth":
+        return even_teeth(n, k)
+    if name == "sharp_teeth":
+        return sharp_teeth(n, k)
+    if name == "shuffled_teeth":
+        return shuffled_teeth(n, k, seed)
+    if name == "distance":
+        return distance(n, k, seed)
+    if name == "exchange":
+        return exchange(n, k, seed)
+    if name == "limited":
+        return limited(n, k, seed)
+    raise ValueError(name)
 
 
 # ------------------------------------------------------------ uint64 runs

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsortrace.so")
 
 SR_INT32, SR_UINT64, SR_FLOAT32 = 0, 1, 2
 DTYPES = {"int32": SR_INT32, "uint64": SR_UINT64, "float32": SR_FLOAT32}
-PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general"}
+PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general", 4: "runs"}
 STATUS = {0: "SR_OK", 1: "SR_ERR_INVALID_ARGUMENT", 2: "SR_ERR_UNSUPPORTED",
           3: "SR_ERR_OUT_OF_MEMORY", 4: "SR_ERR_DEVICE", 5: "SR_ERR_INTERNAL"}
 
@@ -35,7 +35,8 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
 class SrStats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("passes", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("descents", ctypes.c_int64), ("outliers", ctypes.c_int64),
-                ("bytes_moved", ctypes.c_double)]
+                ("bytes_moved", ctypes.c_double), ("run_leaves", ctypes.c_int64),
+                ("merge_passes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class SrServerConfig(ctypes.Structure):
@@ -192,7 +193,8 @@ def last_stats(stream=None) -> dict:
     s = SrStats()
     _check(lib.sr_last_stats(_stream(stream), ctypes.byref(s)), "sr_last_stats")
     return {"path": PATHS.get(s.path, s.path), "passes": s.passes, "n": s.n,
-            "descents": s.descents, "outliers": s.outliers, "bytes_moved": s.bytes_moved}
+            "descents": s.descents, "outliers": s.outliers, "bytes_moved": s.bytes_moved,
+            "run_leaves": s.run_leaves, "merge_passes": s.merge_passes}
 
 
 def workspace_bytes(dtype: str, with_payload: bool, n: int, nseg: int = 0) -> int:

@@ -1,0 +1,169 @@
+"""GPU parity of the natural-run path (SR_PATH_RUNS) against the CPU oracle.
+
+Inputs are the presorted classes of Sec. 2 (k-equal, k-even and k-sharp
+teeth, organ pipes, k-exchange, k-distance) and random concatenations of
+monotone runs with plateaus, at sizes that put run heads inside tiles, on
+tile boundaries and in dense (disordered) tiles.  Every result is compared
+bit for bit with the oracle; the path and pass counts are checked against
+design invariants (they have no value in the paper).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_04471_amd import inputs
+
+from test_gpu_sort import bits, gpu_sort_keys
+
+pytestmark = pytest.mark.gpu
+
+
+def general_passes(n, tile=8192):
+    t = -(-n // tile)
+    return 1 + max(0, (t - 1).bit_length())
+
+
+def check(gpu, a, dtype="int32"):
+    got = gpu_sort_keys(gpu, a, dtype)
+    want = oracle.sort_keys(a)
+    assert np.array_equal(bits(got), bits(want))
+    return gpu.last_stats()
+
+
+@pytest.mark.parametrize("n", [20_000, 262_147, 2_000_000])
+@pytest.mark.parametrize("k", [2, 3, 8, 32])
+def test_teeth_classes(gpu, n, k):
+    for name in ("equal_teeth", "even_teeth", "sharp_teeth"):
+        a = inputs.class_int32(name, n, k, seed=k)
+        st = check(gpu, a)
+        if n // k >= 3 * 8192:  # sections span several tiles: the run plan must pay
+            assert st["path"] == "runs", (name, n, k, st)
+            assert st["merge_passes"] < general_passes(n) - 1, (name, n, k, st)
+        if name == "sharp_teeth" and st["path"] == "runs":
+            # sections hold consecutive value ranges: after the reversals every
+            # leaf continues the previous one, so nothing is merged
+            assert st["run_leaves"] == 1 and st["merge_passes"] == 0, st
+
+
+def test_sharp_teeth_large(gpu):
+    n = 1 << 25
+    a = inputs.sharp_teeth(n, 8)
+    got = gpu_sort_keys(gpu, a, "int32")
+    assert np.array_equal(got, np.arange(1, n + 1, dtype=np.int32))  # closed form
+    st = gpu.last_stats()
+    assert st["path"] == "runs" and st["merge_passes"] == 0, st
+    assert st["passes"] <= 2, st
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_monotone_runs(gpu, seed):
+    """Concatenated runs of random lengths and directions with plateaus, some
+    too short for their own leaf, some disordered stretches."""
+    rng = np.random.default_rng(seed)
+    parts, total = [], 0
+    n_target = [300_000, 1_000_000, 2_500_000][seed % 3]
+    while total < n_target:
+        kind = rng.integers(0, 10)
+        ln = int(rng.integers(1, [60, 3000, 40_000, 200_000][rng.integers(0, 4)]))
+        if kind == 0:   # disordered stretch
+            x = rng.integers(-2**31, 2**31, size=ln, dtype=np.int64)
+        else:
+            steps = rng.integers(0, 4, size=ln)            # zero steps make plateaus
+            steps[rng.random(ln) < 0.3] = 0
+            x = int(rng.integers(-2**30, 2**30)) + np.cumsum(steps)
+            if kind % 2:
+                x = x[::-1]
+        parts.append(np.clip(x, -2**31, 2**31 - 1))
+        total += ln
+    a = np.concatenate(parts)[:n_target].astype(np.int32)
+    check(gpu, a)
+    # the same runs, each shifted above the previous one: ordered leaves
+    b = np.concatenate([p - p.min() + 1 + 10 * i * 2**20 // len(parts) for i, p in enumerate(parts)])
+    b = np.clip(b, -2**31, 2**31 - 1)[:n_target].astype(np.int32)
+    check(gpu, b)
+
+
+def test_constant_stretches_carry_direction(gpu):
+    """Strict directions carried across whole tiles of equal keys."""
+    n1, n2, n3 = 30_000, 50_000, 40_001
+    a = np.concatenate([np.arange(n1), np.full(n2, n1 + 5), np.arange(n1 + 5, n1 + 5 - n3, -1),
+                        np.full(20_000, -3), np.arange(-3, 60_000)]).astype(np.int32)
+    st = check(gpu, a)
+    assert st["path"] == "runs", st
+    b = np.concatenate([np.full(9000, 7), np.arange(7, -20_000, -1), np.full(9000, -5)]).astype(np.int32)
+    check(gpu, b)
+
+
+def test_heads_on_tile_boundaries(gpu):
+    T = 4096
+    for off in (-2, -1, 0, 1, 2):
+        L = 3 * T + off
+        a = np.concatenate([np.arange(L), np.arange(L)[::-1] + 10, np.arange(L) - 5,
+                            np.arange(2 * L)[::-1]]).astype(np.int32)
+        check(gpu, a)
+        s = np.concatenate([np.arange(L)[::-1], np.arange(L, 2 * L), np.arange(3 * L - 1, 2 * L - 1, -1)])
+        got = gpu_sort_keys(gpu, s.astype(np.int32), "int32")
+        assert np.array_equal(got, np.arange(3 * L, dtype=np.int32))
+
+
+def test_sorted_with_dense_patches(gpu):
+    n = 1_500_000
+    a = np.arange(n, dtype=np.int64)
+    rng = np.random.default_rng(3)
+    for start in (100_000, 700_001, 1_400_000):
+        ln = 6000
+        a[start:start + ln] = rng.integers(start - 50_000, start + 50_000, size=ln)
+    st = check(gpu, a.astype(np.int32))
+    assert st["path"] in ("runs", "outlier"), st
+
+
+def test_forced_runs_falls_back_on_random(gpu):
+    gpu.set_option("force_path", 4)
+    try:
+        for n in (10_000, 1_000_003):
+            a = inputs.random_int32(n, seed=n)
+            st = check(gpu, a)
+            assert st["path"] == "general", st
+        a = inputs.class_int32("even_teeth", 1_000_000, 4, seed=0)
+        assert check(gpu, a)["path"] == "runs"
+    finally:
+        gpu.set_option("force_path", -1)
+
+
+def test_exchange_prefers_outlier(gpu):
+    n = 2_000_000
+    for k in (1, 16, 256):
+        a = inputs.class_int32("exchange", n, k, seed=k)
+        st = check(gpu, a)
+        # a few exchanges cost about two passes either way; many only via outliers
+        assert st["path"] in (("outlier", "runs") if k == 1 else ("outlier",)), (k, st)
+
+
+@pytest.mark.parametrize("name", ["distance", "limited", "shuffled_teeth"])
+def test_other_classes(gpu, name):
+    n = 200_003
+    for k in (1, 4, 64):
+        a = inputs.class_int32(name, n, k, seed=k)
+        check(gpu, a)
+
+
+def test_runs_other_dtypes(gpu):
+    n = 1_000_001
+    t = inputs.class_int32("even_teeth", n, 6, seed=0).astype(np.int64)
+    f = (t.astype(np.float32) - 3e5) * np.float32(0.37)
+    f[::200_003] = np.float32(-0.0)
+    st = check(gpu, f, "float32")
+    assert st["path"] == "runs", st
+    u = (t.astype(np.uint64) << np.uint64(40)) + np.uint64(2**63 - 2**62)
+    st = check(gpu, u, "uint64")
+    assert st["path"] == "runs", st
+
+
+def test_runs_switch_off(gpu):
+    a = inputs.class_int32("sharp_teeth", 1_000_000, 4, seed=0)
+    gpu.set_option("runs_path", 0)
+    try:
+        assert check(gpu, a)["path"] == "general"
+    finally:
+        gpu.set_option("runs_path", 1)
+    assert check(gpu, a)["path"] == "runs"

@@ -215,7 +215,15 @@ def test_outlier_path_falls_back(gpu):
     n = 1_000_003
     rot = np.concatenate([np.arange(n // 2, n), np.arange(0, n // 2)]).astype(np.int32)
     assert np.array_equal(gpu_sort_keys(gpu, rot, "int32"), oracle.sort_keys(rot))
-    assert gpu.last_stats()["path"] == "general"     # kept keys not sorted across tiles
+    # kept keys not sorted across tiles: no outlier job; the two ascending
+    # runs take the run path, or the general path once that is switched off
+    assert gpu.last_stats()["path"] == "runs"
+    gpu.set_option("runs_path", 0)
+    try:
+        assert np.array_equal(gpu_sort_keys(gpu, rot, "int32"), oracle.sort_keys(rot))
+        assert gpu.last_stats()["path"] == "general"
+    finally:
+        gpu.set_option("runs_path", 1)
     gpu.set_option("outlier_path", 0)
     try:
         a = inputs.nearly_sorted_int32(n, seed=3)
