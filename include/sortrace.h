@@ -60,10 +60,14 @@ typedef enum {
     SR_PATH_REVERSED = 1,  /* nonincreasing: reversed in place (stable for pairs) */
     SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back */
     SR_PATH_GENERAL = 3,   /* tile sort + merge passes */
-    SR_PATH_RUNS = 4       /* natural runs (keys only): descending runs reversed in
+    SR_PATH_RUNS = 4,      /* natural runs (keys only): descending runs reversed in
                               place, disordered tiles sorted, runs whose values are
                               already in order joined, then a merge tree over the
                               remaining leaves (Sec. 3 natural runs, Sec. 2 Mono) */
+    SR_PATH_FEW = 5        /* few distinct keys (keys only): equal buckets around at
+                              most 64 sampled values -- the GPU form of 3-way
+                              partitioning (Sec. 4, k-limited of Sec. 2); keys
+                              between the sampled values are sorted separately */
 } sr_path;
 
 typedef struct {
@@ -73,7 +77,8 @@ typedef struct {
                               not counted) */
     int64_t n;             /* keys sorted by the call */
     int64_t descents;      /* probe: descents seen (exact when path is SORTED/REVERSED) */
-    int64_t outliers;      /* OUTLIER path: keys moved to the outlier list */
+    int64_t outliers;      /* OUTLIER path: keys moved to the outlier list; FEW path:
+                              keys not equal to any sampled value */
     double bytes_moved;    /* algorithmic HBM bytes: unrounded passes x 2 x n x element bytes */
     int64_t run_leaves;    /* RUNS path: sorted leaves left after the in-order joins */
     int32_t merge_passes;  /* merge passes of the chosen path (RUNS: over its leaves) */
@@ -205,6 +210,9 @@ const char *sr_last_error_message(void);
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
+ *   "few_path"    1 = keys-only sorts may take SR_PATH_FEW (default); 0 = never.
+ *                 A forced SR_PATH_FEW still falls back to SR_PATH_GENERAL when
+ *                 more than a quarter of the keys miss the sampled values.
  *   "runs_path"   1 = keys-only sorts may take SR_PATH_RUNS (default); 0 = never.
  *                 A forced SR_PATH_RUNS still falls back to SR_PATH_GENERAL
  *                 when the run plan exceeds its limits (4096 runs and dense

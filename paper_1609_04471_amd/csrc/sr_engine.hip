@@ -635,6 +635,170 @@ __device__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1
 }
 
 
+
+// -------------------------------------------------------------- few unique
+// FEW job: equal buckets, the data-parallel form of the 3-way partitioning
+// the paper's quicksorts use for few distinct keys (Sec. 2 k-limited class,
+// Sec. 4, Appendix B).  The probe's last workgroup sorts kFewSample evenly
+// spread keys and keeps their distinct values as splitters s_0 < ... <
+// s_{ns-1}.  Bucket 2i+1 holds the keys equal to s_i; bucket 2i the keys
+// strictly between s_{i-1} and s_i (bucket 0: below s_0, bucket 2ns: above
+// s_{ns-1}).
+//   classify  per 4096-key tile: each key's bucket (binary search among the
+//             splitters), bucket counts, and the keys of the "between"
+//             buckets appended to S1[n-m, n) (any order: keys only)
+//   verify    bucket offsets; GENERAL if m > n/4 (U still untouched)
+//   tile sort / merge slots 0 .. P-1: the m between keys are sorted like the
+//             outlier list (U is free: every equal key is known from its
+//             splitter and count)
+//   merge slot P: every output position is filled from its bucket -- the
+//             splitter value, or the next sorted between key
+// Keys equal under the order are bit-identical, so writing the splitter
+// reproduces them exactly.  For few-unique input m = 0: one read and one
+// write of the array.
+constexpr int kFewMax = 64;
+constexpr int kFewBuckets = 2 * kFewMax + 1;
+constexpr int kFewSample = 1024;
+constexpr size_t kFewLdsBytes = 8 * (2 * kFewBuckets + 1) + 8 * kFewMax;  // few_place's table copy
+
+struct FewTable {
+    unsigned long long ns;                    // splitters
+    unsigned long long split[kFewMax];        // encoded, ascending, distinct
+    unsigned long long cnt[kFewBuckets];      // keys per bucket
+    long long off[kFewBuckets + 1];           // first output position of each bucket
+    long long bpre[kFewBuckets];              // between keys in earlier buckets
+};
+
+template <class U>
+__device__ __forceinline__ int few_bucket(const U* sp, int ns, U u) {
+    int lo = 0, hi = ns;  // splitters below u
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sp[mid] < u) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < ns && sp[lo] == u) ? 2 * lo + 1 : 2 * lo;
+}
+
+// Bucket counts and between keys of the 4096-key tile [c0, c1) (256 threads).
+template <class C>
+__device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int64_t c1, Ctl* ctl, FewTable* ft,
+                          typename C::S* s1) {
+    using U = typename C::U;
+    constexpr int R = kClsTC / kClsWG;
+    __shared__ U sp[kFewMax];
+    __shared__ unsigned int hist[kFewBuckets];
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int ns = (int)ft->ns;
+    const int nb = 2 * ns + 1;
+    for (int i = tid; i < ns; i += kClsWG) sp[i] = (U)ft->split[i];
+    for (int b = tid; b < nb; b += kClsWG) hist[b] = 0;
+    typename C::S x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + r * kClsWG + tid;
+        if (q < c1) x[r] = keys[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + r * kClsWG + tid;
+        bool between = false;
+        if (q < c1) {
+            const int b = few_bucket<U>(sp, ns, C::enc(x[r]));
+            atomicAdd(&hist[b], 1u);
+            between = (b & 1) == 0;
+        }
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(between);
+        if (mask != 0ull) {
+            const int leader = __builtin_ctzll(mask);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&ctl->m, (unsigned long long)__builtin_popcountll(mask));
+            base = __shfl(base, leader);
+            if (between) {
+                const unsigned long long rank = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+                s1[n - 1 - (int64_t)(base + rank)] = x[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += kClsWG)
+        if (hist[b] != 0u) atomicAdd(&ft->cnt[b], (unsigned long long)hist[b]);
+}
+
+// Bucket offsets and the job (thread 0 of the verify workgroup).
+__device__ void few_plan(Ctl* ctl, int64_t n, FewTable* ft, int64_t T_sort) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long m = ctl->m;
+    const int nb = 2 * (int)ft->ns + 1;
+    long long o = 0, bp = 0;
+    for (int b = 0; b < nb; ++b) {
+        ft->off[b] = o;
+        ft->bpre[b] = bp;
+        o += (long long)ft->cnt[b];
+        if ((b & 1) == 0) bp += (long long)ft->cnt[b];
+    }
+    ft->off[nb] = o;
+    if (o != n || (unsigned long long)bp != m || 4 * m > (unsigned long long)n) {
+        ctl->path = SR_PATH_GENERAL;
+        ctl->m = 0;
+        ctl->job_passes = 0;
+        return;
+    }
+    ctl->job_passes = ceil_log2_dev(((int64_t)m + T_sort - 1) / T_sort);
+}
+
+// Merge slot P of the FEW job: U[p] for every p, grid-stride over blocks of
+// WG x 8 outputs; lds holds the table (at least 8 * (2 * kFewBuckets + 1) +
+// 8 * kFewMax bytes).
+template <class C, int WG>
+__device__ void few_place(typename C::S* U, const typename C::S* X0, int64_t n, const FewTable* ft, void* lds) {
+    using S = typename C::S;
+    constexpr int IT = 8;
+    long long* off = static_cast<long long*>(lds);
+    long long* bpre = off + kFewBuckets + 1;
+    S* spv = reinterpret_cast<S*>(bpre + kFewBuckets);
+    const int tid = threadIdx.x;
+    const int ns = (int)ft->ns;
+    const int nb = 2 * ns + 1;
+    for (int b = tid; b <= nb; b += WG) off[b] = ft->off[b];
+    for (int b = tid; b < nb; b += WG) bpre[b] = ft->bpre[b];
+    for (int i = tid; i < ns; i += WG) spv[i] = C::dec((typename C::U)ft->split[i]);
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * WG * IT; base < n; base += (int64_t)gridDim.x * WG * IT) {
+        const int64_t p0 = base + (int64_t)tid * IT;
+        if (p0 >= n) continue;
+        int lo = 0, hi = nb - 1;  // last bucket starting at or before p0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= p0) lo = mid;
+            else hi = mid - 1;
+        }
+        int b = lo;
+        constexpr int VN = 16 / sizeof(S);
+        V16<S> v[IT / VN];
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int64_t p = p0 + r;
+            S val{};
+            if (p < n) {
+                while (off[b + 1] <= p) ++b;
+                val = (b & 1) ? spv[b >> 1] : X0[bpre[b] + (p - off[b])];
+            }
+            v[r / VN].v[r % VN] = val;
+        }
+        if (p0 + IT <= n && aligned16(U + p0)) {
+#pragma unroll
+            for (int q = 0; q < IT / VN; ++q) reinterpret_cast<V16<S>*>(U + p0)[q] = v[q];
+        } else {
+#pragma unroll
+            for (int r = 0; r < IT; ++r)
+                if (p0 + r < n) U[p0 + r] = v[r / VN].v[r % VN];
+        }
+    }
+}
+
 // ============================================================== kernels
 
 // Tile-sort launch.  GENERAL / OUTLIER: the tile sort of the job's array
@@ -756,14 +920,22 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
                                               int64_t n, int M, int64_t T, int k, const Ctl* ctl,
-                                              const RunArea* ra) {
+                                              const RunArea* ra, const FewTable* ft) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename MC::Smem sm;
+    static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
     if constexpr (!PAIRS) {
-        if (ra != nullptr && ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
-            runs_merge<MC, S>(sm, ra, U, S1, k);
-            return;
+        if (ctl != nullptr) {
+            const int path = ld_agent(&ctl->path);
+            if (ra != nullptr && path == SR_PATH_RUNS) {
+                runs_merge<MC, S>(sm, ra, U, S1, k);
+                return;
+            }
+            if (ft != nullptr && path == SR_PATH_FEW && k == ld_agent(&ctl->job_passes)) {
+                few_place<C, WG>(U, S1 + (n - (int64_t)ld_agent(&ctl->m)), n, ft, &sm);
+                return;
+            }
         }
     }
     const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
@@ -778,7 +950,8 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
-                                                      const int64_t* co, const Ctl* ctl, const RunArea* ra) {
+                                                      const int64_t* co, const Ctl* ctl, const RunArea* ra,
+                                                      const FewTable* ft) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
     using MC = typename MP::MC;
     using S = typename C::S;
@@ -786,10 +959,18 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         typename MP::Smem p;
         typename MC::Smem c;
     } sm;
+    static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
     if constexpr (!PAIRS) {
-        if (ra != nullptr && ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
-            runs_merge<MC, S>(sm.c, ra, U, S1, k);
-            return;
+        if (ctl != nullptr) {
+            const int path = ld_agent(&ctl->path);
+            if (ra != nullptr && path == SR_PATH_RUNS) {
+                runs_merge<MC, S>(sm.c, ra, U, S1, k);
+                return;
+            }
+            if (ft != nullptr && path == SR_PATH_FEW && k == ld_agent(&ctl->job_passes)) {
+                few_place<C, WG>(U, S1 + (n - (int64_t)ld_agent(&ctl->m)), n, ft, &sm);
+                return;
+            }
         }
     }
     const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
@@ -818,9 +999,16 @@ template <class C>
 __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, int64_t n, Ctl* ctl,
                                                      unsigned int* flags, unsigned long long* tfirst,
                                                      unsigned long long* tlast, unsigned long long* tcount,
-                                                     int runs_ok, RunTile* rdesc) {
+                                                     int runs_ok, RunTile* rdesc, FewTable* ft,
+                                                     typename C::S* s1) {
     using U = typename C::U;
     const int path = ld_agent(&ctl->path);
+    if (path == SR_PATH_FEW) {
+        const int64_t f0 = (int64_t)blockIdx.x * kClsTC;
+        const int64_t f1 = (f0 + kClsTC) < n ? (f0 + kClsTC) : n;
+        few_count<C>(keys, n, f0, f1, ctl, ft, s1);
+        return;
+    }
     const bool do_runs = runs_ok && (path == SR_PATH_RUNS || path == SR_PATH_OUTLIER);
     if (path != SR_PATH_OUTLIER && !do_runs) return;
     __shared__ U sk[kClsW];
@@ -1100,8 +1288,12 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
                                                    const unsigned long long* tlast, const unsigned long long* tcount,
                                                    unsigned long long* kpref_t, int64_t T_sort,
                                                    const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
-                                                   int runs_ok, int64_t merge_ch, int M) {
+                                                   int runs_ok, int64_t merge_ch, int M, FewTable* ft) {
     const int path0 = ld_agent(&ctl->path);
+    if (path0 == SR_PATH_FEW) {
+        few_plan(ctl, n, ft, T_sort);
+        return;
+    }
     const bool want_runs =
         runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->force_path != SR_PATH_OUTLIER));
     __shared__ double s_ocost;
@@ -1220,7 +1412,7 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
 // finish turns the counters into the plan and clears them.
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
-                                                    unsigned long long* slots, int jobs_ok) {
+                                                    unsigned long long* slots, int jobs_ok, FewTable* ft) {
     using U = typename C::U;
     using S = typename C::S;
     constexpr int VN = 16 / sizeof(S);
@@ -1244,7 +1436,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
             sd += x > y ? 1 : 0;
-            sp += 1;
+            sp += x == y ? (1ull << 32) + 1 : 1;  // pairs (low half), equal pairs (high half)
             if (i + 1 < npairs) {
                 const U z = C::enc(keys[i + 2]);
                 if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << 32;
@@ -1354,6 +1546,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             for (int q = 0; q < 4; ++q) red[q][wave] = acc[q];
         __syncthreads();
     }
+    __shared__ int s_path, s_force;
+    __shared__ unsigned long long s_desc, s_asc;
     if (last && tid == 0) {
         unsigned long long tot[4] = {0, 0, 0, 0};
         for (int w = 0; w < kProbeWG / kWave; ++w)
@@ -1362,32 +1556,106 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         const unsigned long long asc = tot[1];
         const unsigned long long sdesc = tot[2] & 0xFFFFFFFFull;
         const unsigned long long sturn = tot[2] >> 32;
-        const unsigned long long spairs = tot[3];
+        const unsigned long long spairs = tot[3] & 0xFFFFFFFFull;
+        const unsigned long long sequal = tot[3] >> 32;
         const bool mixed = ld_agent(&ctl->mixed) != 0;
-        const bool outlier_ok = (jobs_ok & 1) != 0, runs_ok = (jobs_ok & 2) != 0;
+        const bool outlier_ok = (jobs_ok & 1) != 0, runs_ok = (jobs_ok & 2) != 0, few_ok = (jobs_ok & 4) != 0;
         int path;
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
         else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
         else if (outlier_ok && sdesc * 16 <= spairs) path = SR_PATH_OUTLIER;
+        else if (few_ok && sequal * 128 >= spairs) path = SR_PATH_FEW;  // confirmed by the sample below
         else if (runs_ok && sturn * 64 <= spairs) path = SR_PATH_RUNS;
         else path = SR_PATH_GENERAL;
         const int force = ctl->force_path;
-        if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok) || (force == SR_PATH_RUNS && runs_ok))
+        if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok) || (force == SR_PATH_RUNS && runs_ok) ||
+            (force == SR_PATH_FEW && few_ok))
             path = force;
-        ctl->path = path;
-        ctl->reserved[0] = desc;   // kept for sr_last_stats
-        ctl->reserved[1] = asc;
-        ctl->reserved[2] = 0;
-        ctl->reserved[3] = 0;
-        ctl->mixed = 0;
-        ctl->ticket = 0;
-        ctl->m = 0;
-        ctl->job_passes = 0;
-        ctl->n_kept = 0;
-        ctl->bad_join = 0;
-        ctl->ticket2 = 0;
-        unsigned int ep = (ctl->epoch + 1u) & 0xFFFFFFu;
-        ctl->epoch = ep == 0u ? 1u : ep;
+        // fallback if the sample shows too many distinct keys
+        s_path = path == SR_PATH_FEW && force != SR_PATH_FEW
+                     ? -((runs_ok && sturn * 64 <= spairs) ? SR_PATH_RUNS : SR_PATH_GENERAL) - 10
+                     : path;
+        s_force = force == SR_PATH_FEW;
+        s_desc = desc;
+        s_asc = asc;
+    }
+    if (last) {
+        __syncthreads();
+        int path = s_path;
+        if (path == SR_PATH_FEW || path <= -10) {
+            // FEW: the distinct keys of kFewSample evenly spread samples,
+            // sorted in LDS (bitonic), become the splitters if there are at
+            // most kFewMax of them (or, when forced, the first kFewMax)
+            __shared__ U fs[kFewSample];
+            __shared__ int s_cnt[kProbeWG / kWave];
+            for (int i = tid; i < kFewSample; i += kProbeWG) fs[i] = C::enc(keys[(int64_t)i * n / kFewSample]);
+            __syncthreads();
+            for (int k = 2; k <= kFewSample; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = tid; i < kFewSample / 2; i += kProbeWG) {
+                        const int lo = 2 * i - (i & (j - 1));
+                        const int hi = lo + j;
+                        const bool up = (lo & k) == 0;
+                        const U a = fs[lo], b = fs[hi];
+                        if ((a > b) == up) {
+                            fs[lo] = b;
+                            fs[hi] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            constexpr int PER = kFewSample / kProbeWG;
+            int c = 0;
+            bool first[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int i = tid * PER + r;
+                first[r] = i == 0 || fs[i] != fs[i - 1];
+                c += first[r] ? 1 : 0;
+            }
+            int xc = c;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(xc, o);
+                if ((int)__lane_id() >= o) xc += y;
+            }
+            if (__lane_id() == kWave - 1) s_cnt[wave] = xc;
+            __syncthreads();
+            int total = 0, pre = xc - c;
+            for (int w = 0; w < kProbeWG / kWave; ++w) {
+                total += s_cnt[w];
+                if (w < wave) pre += s_cnt[w];
+            }
+            const bool take = total <= kFewMax || s_force;
+            if (take) {
+#pragma unroll
+                for (int r = 0; r < PER; ++r)
+                    if (first[r] && pre < kFewMax) ft->split[pre++] = (unsigned long long)fs[tid * PER + r];
+                const int ns = total < kFewMax ? total : kFewMax;
+                for (int b = tid; b < 2 * ns + 1; b += kProbeWG) ft->cnt[b] = 0;
+                if (tid == 0) ft->ns = (unsigned long long)ns;
+                path = SR_PATH_FEW;
+            } else {
+                path = -path - 10;
+            }
+        }
+        if (tid == 0) {
+            ctl->path = path;
+            ctl->reserved[0] = s_desc;  // kept for sr_last_stats
+            ctl->reserved[1] = s_asc;
+            ctl->reserved[2] = 0;
+            ctl->reserved[3] = 0;
+            ctl->mixed = 0;
+            ctl->ticket = 0;
+            ctl->m = 0;
+            ctl->job_passes = 0;
+            ctl->n_kept = 0;
+            ctl->bad_join = 0;
+            ctl->ticket2 = 0;
+            unsigned int ep = (ctl->epoch + 1u) & 0xFFFFFFu;
+            ctl->epoch = ep == 0u ? 1u : ep;
+        }
     }
 }
 
@@ -1687,7 +1955,8 @@ int g_force_path = -1;
 bool g_profile = false;
 int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
 bool g_outlier_enabled = true;
-bool g_runs_enabled = true;                      // allow the RUNS path for keys-only sorts                   // allow the OUTLIER path for keys-only sorts
+bool g_runs_enabled = true;                      // allow the RUNS path for keys-only sorts
+bool g_few_enabled = true;                       // allow the FEW path for keys-only sorts                   // allow the OUTLIER path for keys-only sorts
 int g_tile_variant = -1;  // -1 auto (1024 x 8 below partition_min_n), 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
 int g_merge_items = 8;    // fused merge: outputs per thread (16 or 8, 32-bit keys only)
 
@@ -1765,6 +2034,10 @@ constexpr size_t kHdrBytes = 64 * 1024;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
 static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 + (kProbeMaxGrid / kProbeGroup + 1) * 256 <= kHdrBytes,
               "probe slots and group counters");
+constexpr size_t kFewOff = 48 * 1024;  // FEW splitter table inside the header
+static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 + (kProbeMaxGrid / kProbeGroup + 1) * 256 <= kFewOff &&
+                  kFewOff + sizeof(FewTable) <= kHdrBytes,
+              "few-unique table");
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -1924,7 +2197,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     const int64_t nchunks = cdiv(n, CH);
     const bool outlier_ok = !PAIRS && g_outlier_enabled;
     const bool runs_ok = !PAIRS && g_runs_enabled;
-    const bool scan_ok = outlier_ok || runs_ok;
+    const bool few_ok = !PAIRS && g_few_enabled;
+    const bool scan_ok = outlier_ok || runs_ok || few_ok;
     const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
     const size_t co_bytes = round_up((size_t)(nchunks + 2) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
@@ -1948,12 +2222,13 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     const int64_t merge_ch = use_partition ? CH : (merge8 ? (int64_t)TN::MWG * 8 : CH);
     RunTile* rdesc = nullptr;
     RunArea* rarea = nullptr;
+    FewTable* ftab = few_ok ? reinterpret_cast<FewTable*>(static_cast<char*>(ws->hdr) + kFewOff) : nullptr;
 
     {
         ProfScope ps(ls, "probe");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
         hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
-                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0));
+                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0), ftab);
         SR_LAUNCH_CHECK("probe");
     }
     if (scan_ok) {
@@ -1970,7 +2245,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         {
             ProfScope ps(ls, "classify");
             hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n, ctl,
-                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc);
+                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc, ftab, skeys);
             SR_LAUNCH_CHECK("classify");
         }
         {
@@ -1978,7 +2253,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
             hipLaunchKernelGGL(k_verify<C>, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
                                (const unsigned long long*)tcount, kpref_t, (int64_t)T, (const S*)keys,
-                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M);
+                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab);
             SR_LAUNCH_CHECK("verify");
         }
         ProfScope ps(ls, "scatter");
@@ -2021,7 +2296,8 @@ tile_done:
             auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
-                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea);
+                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
+                               (const FewTable*)ftab);
             SR_LAUNCH_CHECK("merge");
         } else {
             ProfScope ps(ls, "merge");
@@ -2030,14 +2306,14 @@ tile_done:
                 if (merge8) {
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)cdiv(n, TN::MWG * 8)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
-                                       (const Ctl*)ctl, (const RunArea*)rarea);
+                                       (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab);
                     done = true;
                 }
             }
             if (!done)
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0,
                                    ls, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl,
-                                   (const RunArea*)rarea);
+                                   (const RunArea*)rarea, (const FewTable*)ftab);
             SR_LAUNCH_CHECK("merge");
         }
     }
@@ -2473,6 +2749,15 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             eq = 2.0 + (1.0 + h.job_passes) * m / (double)lc.n;
             break;
         }
+        case SR_PATH_FEW: {
+            // bucket count (n read, m written) + sort of the m between keys
+            // + fill (n written, m read)
+            const double m = (double)h.m;
+            out->outliers = (int64_t)h.m;
+            out->merge_passes = h.job_passes + 1;
+            eq = 1.0 + (2.0 + h.job_passes) * m / (double)lc.n;
+            break;
+        }
         case SR_PATH_RUNS: {
             // run scan (n read) + reversal and dense tile sorts + merge tree
             out->run_leaves = (int64_t)h.run[0];
@@ -2512,7 +2797,7 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (!name) return fail(SR_ERR_INVALID_ARGUMENT, "name is NULL");
     std::lock_guard<std::mutex> lk(g_mu);
     if (std::strcmp(name, "force_path") == 0) {
-        if (value < -1 || value > SR_PATH_RUNS) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
+        if (value < -1 || value > SR_PATH_FEW) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
         g_force_path = (int)value;
         return SR_OK;
     }
@@ -2539,6 +2824,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "outlier_path") == 0) {
         if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "outlier_path is 0 or 1");
         g_outlier_enabled = value != 0;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "few_path") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "few_path is 0 or 1");
+        g_few_enabled = value != 0;
         return SR_OK;
     }
     if (std::strcmp(name, "runs_path") == 0) {

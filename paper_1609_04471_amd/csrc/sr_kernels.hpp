@@ -449,7 +449,8 @@ struct MergePersistent {
 // read from the plan in the control block.  GENERAL sorts the user buffer U
 // with ping-pong partner S1 in M merge passes.  OUTLIER sorts the m outliers
 // (stored at S1[n-m, n)) with partner U in P passes, then merge slot P merges
-// the kept keys S1[0, n-m) with the sorted outliers into U.
+// the kept keys S1[0, n-m) with the sorted outliers into U.  FEW sorts its m
+// between-bucket keys the same way; its slot P is the fill pass.
 template <class S>
 struct PassView {
     const S* src;
@@ -478,7 +479,7 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
         v.n = n;
         v.width = T << k;
         v.active = true;
-    } else if (path == 2 /* SR_PATH_OUTLIER */) {
+    } else if (path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW: slot P is its fill pass */) {
         const int64_t m = (int64_t)ld_agent(&ctl->m);
         const int P = ld_agent(&ctl->job_passes);
         S* X0 = S1 + (n - m);
@@ -489,7 +490,7 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
             v.n = m;
             v.width = T << k;
             v.active = true;
-        } else if (k == P) {
+        } else if (k == P && path == 2) {
             v.src = S1;
             v.dst = U;
             v.n = n;
@@ -524,7 +525,7 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         v.pdst = (M & 1) ? PS1 : PU;
         v.n = n;
         v.active = true;
-    } else if (path == 2 /* SR_PATH_OUTLIER */) {
+    } else if (path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW */) {
         const int64_t m = (int64_t)ld_agent(&ctl->m);
         const int P = ld_agent(&ctl->job_passes);
         S* X0 = S1 + (n - m);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsortrace.so")
 
 SR_INT32, SR_UINT64, SR_FLOAT32 = 0, 1, 2
 DTYPES = {"int32": SR_INT32, "uint64": SR_UINT64, "float32": SR_FLOAT32}
-PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general", 4: "runs"}
+PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general", 4: "runs", 5: "few"}
 STATUS = {0: "SR_OK", 1: "SR_ERR_INVALID_ARGUMENT", 2: "SR_ERR_UNSUPPORTED",
           3: "SR_ERR_OUT_OF_MEMORY", 4: "SR_ERR_DEVICE", 5: "SR_ERR_INTERNAL"}
 

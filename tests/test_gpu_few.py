@@ -1,0 +1,117 @@
+"""GPU parity of the few-distinct-keys path (SR_PATH_FEW) against the oracle.
+
+Few-unique inputs (the Table 1 type and the k-limited class of Sec. 2),
+with and without keys that the probe's sample misses (they go through the
+separate between-key sort), float32 specials and uint64 keys.  Every result
+is compared bit for bit with the oracle; paths are checked against design
+invariants.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_04471_amd import inputs
+
+from test_gpu_sort import bits, gpu_sort_keys
+
+pytestmark = pytest.mark.gpu
+
+
+def check(gpu, a, dtype="int32"):
+    got = gpu_sort_keys(gpu, a, dtype)
+    assert np.array_equal(bits(got), bits(oracle.sort_keys(a)))
+    return gpu.last_stats()
+
+
+@pytest.mark.parametrize("n", [8193, 20_000, 65_537, 300_001, 2_000_000, 5_000_011])
+def test_few_unique_type(gpu, n):
+    a = inputs.few_unique_int32(n, seed=n)
+    st = check(gpu, a)
+    assert st["path"] == "few" and st["outliers"] == 0, st
+    assert st["passes"] == 1, st
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8, 12])
+def test_k_limited(gpu, k):
+    n = 1_000_003
+    a = inputs.class_int32("limited", n, k, seed=k)
+    st = check(gpu, a)
+    if k <= 6:
+        assert st["path"] == "few", st
+    else:  # more distinct values than splitters
+        assert st["path"] != "few" or st["outliers"] > 0, st
+
+
+@pytest.mark.parametrize("n", [100_000, 2_000_000, 5_000_011])
+@pytest.mark.parametrize("frac", [0.001, 0.03, 0.3])
+def test_between_keys(gpu, n, frac):
+    rng = np.random.default_rng(int(n * frac * 1000) % 2**32)
+    vals = rng.integers(-2**31, 2**31, size=20, dtype=np.int64)
+    a = vals[rng.integers(0, 20, size=n)]
+    other = rng.random(n) < frac
+    a[other] = rng.integers(-2**31, 2**31, size=int(other.sum()), dtype=np.int64)
+    a = a.astype(np.int32)
+    st = check(gpu, a)
+    if frac < 0.25:
+        assert st["path"] == "few", st
+        assert st["outliers"] > 0, st
+    else:
+        assert st["path"] != "few", st
+
+
+def test_rare_values_missed_by_the_sample(gpu):
+    n = 3_000_001
+    a = inputs.few_unique_int32(n, seed=9)
+    rng = np.random.default_rng(4)
+    pos = rng.choice(n, size=37, replace=False)
+    a[pos] = np.arange(37, dtype=np.int32) * 1000 - 17
+    st = check(gpu, a)
+    assert st["path"] == "few" and 0 < st["outliers"] <= 37, st
+
+
+def test_float_specials(gpu):
+    n = 1_200_007
+    pool = np.array([0x7FC00000, 0xFFC00000, 0x7F800001, 0xFF800000, 0x7F800000, 0x80000000, 0x00000000,
+                     0x3F800000, 0xBFC00000, 0x00000001, 0x80000001], dtype=np.uint32).view(np.float32)
+    rng = np.random.default_rng(5)
+    f = pool[rng.integers(0, pool.size, size=n)]
+    st = check(gpu, f, "float32")
+    assert st["path"] == "few", st
+
+
+def test_uint64(gpu):
+    n = 2_000_003
+    rng = np.random.default_rng(6)
+    vals = rng.integers(0, 2**63, size=13, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    u = vals[rng.integers(0, 13, size=n)]
+    u[::50_021] = np.uint64(2**64 - 1)
+    st = check(gpu, u, "uint64")
+    assert st["path"] == "few", st
+
+
+def test_large_closed_form(gpu):
+    n = 1 << 26
+    a = inputs.few_unique_int32(n, seed=26)
+    got = gpu_sort_keys(gpu, a, "int32")
+    v, c = np.unique(a, return_counts=True)
+    assert np.array_equal(got, np.repeat(v, c))
+    st = gpu.last_stats()
+    assert st["path"] == "few" and st["passes"] == 1, st
+
+
+def test_forced_and_switched_off(gpu):
+    gpu.set_option("force_path", 5)
+    try:
+        for n in (10_000, 1_000_003):
+            a = inputs.random_int32(n, seed=n)
+            assert check(gpu, a)["path"] == "general"  # the sample's values cover too few keys
+        b = inputs.few_unique_int32(500_000, seed=1)
+        assert check(gpu, b)["path"] == "few"
+    finally:
+        gpu.set_option("force_path", -1)
+    gpu.set_option("few_path", 0)
+    try:
+        b = inputs.few_unique_int32(500_000, seed=2)
+        assert check(gpu, b)["path"] == "general"
+    finally:
+        gpu.set_option("few_path", 1)
