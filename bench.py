@@ -75,8 +75,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-seg", action="store_true", help="skip the batched-segments section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-classes", action="store_true", help="skip the Sec. 2 presorted-class section")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve"],
+    ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve",
+                                       "classes"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -235,6 +237,12 @@ def main():
         torch.cuda.synchronize()
     result.update(per_type_256M=per_big or None, roofline=roofline, copy_GBps=round(copy_gbps, 1) if copy_gbps else None)
 
+    # ------------------------------------------------------------ Sec. 2 classes
+    classes = None
+    if not args.no_classes and args.only in (None, "classes"):
+        classes = classes_section(args, torch, np, inputs, sortrace, dev, stream)
+    result["classes"] = classes
+
     # ------------------------------------------------------------ batched segments
     seg = None
     if not args.no_seg and args.only in (None, "seg"):
@@ -336,10 +344,80 @@ def main():
         "per_type_256M": result.get("per_type_256M"),
         "copy_GBps": result.get("copy_GBps"),
         "segmented_4096": result.get("segmented"),
+        "presorted_classes": result.get("classes"),
         "serving": result.get("serving"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def classes_section(args, torch, np, inputs, sortrace, dev, stream):
+    """The presorted classes of Sec. 2 as in Tables 2-3: n = 2M, k = 2^0..2^8,
+    each input sorted by the adaptive plan and by the forced general path
+    (tile sort + every merge pass); mean times over k per class.  Two 256M
+    teeth inputs show the pass counts at scale.  k-shuffled teeth is left out
+    (its generator is a sequential shuffle; the GPU treats it as random)."""
+    names = ("equal_teeth", "even_teeth", "sharp_teeth", "distance", "exchange", "limited")
+    ks = [1 << i for i in range(9)]
+
+    def time_sort(src, work, reps, force=None):
+        if force is not None:
+            sortrace.set_option("force_path", force)
+        try:
+            times = []
+            for i in range(reps + 1):
+                work.copy_(src)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                sortrace.sort_keys(work)
+                b.record(stream)
+                torch.cuda.synchronize()
+                if i > 0:
+                    times.append(a.elapsed_time(b))
+            st = sortrace.last_stats()
+        finally:
+            if force is not None:
+                sortrace.set_option("force_path", -1)
+        assert bool((work[1:] >= work[:-1]).all())
+        return statistics.median(times), st
+
+    out = {}
+    n = N_SMALL
+    work = torch.empty(n, dtype=torch.int32, device=dev)
+    for ci, name in enumerate(names):
+        rows = []
+        for k in ks:
+            src = torch.from_numpy(inputs.class_int32(name, n, k, inputs.seed_for(6, ci, k))).to(dev)
+            ms, st = time_sort(src, work, 10)
+            gms, _ = time_sort(src, work, 5, force=3)
+            rows.append((k, ms, gms, st["path"], st["passes"]))
+        mean = statistics.mean(r[1] for r in rows)
+        gmean = statistics.mean(r[2] for r in rows)
+        paths = {}
+        for r in rows:
+            paths[r[3]] = paths.get(r[3], 0) + 1
+        out[name] = {"ms_mean_over_k": round(mean, 5), "Mkeys_s": round(n / (mean / 1e3) / 1e6, 1),
+                     "general_ms_mean": round(gmean, 5), "speedup_vs_general": round(gmean / mean, 2),
+                     "paths": paths, "passes": {str(r[0]): r[4] for r in rows}}
+        log(f"classes 2M {name}: {out[name]}")
+    del work
+    big = {}
+    if not args.no_big:
+        work = torch.empty(N_BIG, dtype=torch.int32, device=dev)
+        for name, k in (("sharp_teeth", 8), ("even_teeth", 8), ("equal_teeth", 64)):
+            log(f"generating 256M {name} k={k}")
+            src = torch.from_numpy(inputs.class_int32(name, N_BIG, k, 0)).to(dev)
+            ms, st = time_sort(src, work, 3)
+            gms, gst = time_sort(src, work, 1, force=3)
+            big[f"{name}_k{k}"] = {"ms": round(ms, 4), "Mkeys_s": round(N_BIG / (ms / 1e3) / 1e6, 1),
+                                   "path": st["path"], "passes": st["passes"],
+                                   "merge_passes": st["merge_passes"], "leaves": st["run_leaves"],
+                                   "general_ms": round(gms, 4), "general_passes": gst["passes"]}
+            log(f"classes 256M {name} k={k}: {big[f'{name}_k{k}']}")
+            del src
+        del work
+        torch.cuda.synchronize()
+    return {"n": n, "k": ks, "per_class_2M": out, "n_big": N_BIG if big else None, "big": big or None}
 
 
 def serve_section(args, torch, np, inputs, sortrace, dev):

@@ -70,12 +70,15 @@ struct Ctl {
     unsigned int ticket3;             // OUTLIER: classify workgroups finished
     unsigned int epoch;               // call counter stamped into the look-back status words
     int job_passes;                   // OUTLIER: merge passes of the outlier sort
-    int pad0;
+    int dual;                         // OUTLIER beside a run plan (the sample's turning points are rare)
     unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
     unsigned long long run[4];        // RUNS: merge leaves, merge passes, keys reversed, keys in dense pieces
 };
 
-// Plain relaxed agent-scope accessors (coherent across the XCDs' L2s).
+// Plain relaxed agent-scope accessors (coherent across the XCDs' L2s), for
+// words that other workgroups of the same launch write.  Plan fields written
+// by an earlier launch on the stream are read with plain loads: the launch
+// boundary orders them.
 __device__ __forceinline__ unsigned int ld_agent(const unsigned int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -60,7 +60,7 @@ constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over it
 constexpr unsigned int kProbeGroup = 32;  // probe workgroups per first-level ticket counter
 
 __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
-    return ctl == nullptr || ld_agent(&ctl->path) == want;
+    return ctl == nullptr || ctl->path == want;
 }
 
 // Outlier-path tile geometry (used by the RUNS job too).
@@ -69,7 +69,7 @@ constexpr int kClsPer = 17;
 constexpr int kClsW = kClsWG * kClsPer;  // 4352-key window
 constexpr int kClsTC = 4096;             // core keys per tile
 constexpr int kClsH = (kClsW - kClsTC) / 2;
-constexpr int kClsMaxIter = 48;
+constexpr int kClsMaxIter = 10;  // more rounds: not outlier-shaped (falls back)
 
 __device__ __forceinline__ int ceil_log2_dev(int64_t x) {
     int r = 0;
@@ -208,28 +208,27 @@ __device__ void runscan_lds(const U* sk, int64_t n, int64_t c0, int64_t c1, int6
     if (tid == 0) s_first = -1;
     const int64_t qend = c1 < n - 1 ? c1 : n - 1;  // pairs of this tile: [c0, qend)
     const int b0 = tid * PER;
-    int d[PER];
-    int lastv = 0, firstv = 0;
+    // bit r: pair b0 + r is strict / descending
+    unsigned int strict = 0u, descm = 0u;
     U mn = ~(U)0, mx = 0;
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
         const int64_t q = c0 + b0 + r;
-        int sg = 0;
         if (q < c1) {
             const U a = sk[q - w0];
             mn = a < mn ? a : mn;
             mx = a > mx ? a : mx;
             if (q < qend) {
                 const U b = sk[q - w0 + 1];
-                sg = a < b ? 1 : (a > b ? -1 : 0);
+                strict |= (a != b ? 1u : 0u) << r;
+                descm |= (a > b ? 1u : 0u) << r;
             }
         }
-        d[r] = sg;
-        if (sg != 0) {
-            lastv = ((b0 + r + 1) << 1) | (sg < 0 ? 1 : 0);
-            if (firstv == 0) firstv = lastv;
-        }
     }
+    const int rl = 31 - __builtin_clz(strict | 1u);  // last strict pair (valid when strict != 0)
+    const int lastv = strict ? ((b0 + rl + 1) << 1) | (int)((descm >> rl) & 1u) : 0;
+    const int rf = __builtin_ctz(strict | 0x80000000u);
+    const int firstv = strict ? ((b0 + rf + 1) << 1) | (int)((descm >> rf) & 1u) : 0;
     int incl = lastv;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -252,15 +251,15 @@ __device__ void runscan_lds(const U* sk, int64_t n, int64_t c0, int64_t c1, int6
     if (lane == 0) in = 0;
     for (int w = 0; w < wave; ++w) in = s_last[w] > in ? s_last[w] : in;
     if (in == 0 && firstv != 0) s_first = firstv;  // the tile's first strict pair
+    // turnings: strict pairs whose previous strict pair has the other direction
     int cnt = 0;
     {
-        int pv = in;
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            if (d[r] != 0) {
-                if (pv != 0 && ((pv & 1) ? -1 : 1) == -d[r]) ++cnt;
-                pv = ((b0 + r + 1) << 1) | (d[r] < 0 ? 1 : 0);
-            }
+        int pd = in == 0 ? -1 : (in & 1);
+        for (unsigned int m = strict; m != 0u; m &= m - 1u) {
+            const int r = __builtin_ctz(m);
+            const int dd = (int)((descm >> r) & 1u);
+            if (pd >= 0 && pd != dd) ++cnt;
+            pd = dd;
         }
     }
     int xc = cnt;
@@ -277,14 +276,12 @@ __device__ void runscan_lds(const U* sk, int64_t n, int64_t c0, int64_t c1, int6
         if (w < wave) hpre += s_cnt[w];
     }
     if (total <= kRunHeads && cnt > 0) {
-        int pv = in;
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            if (d[r] != 0) {
-                if (pv != 0 && ((pv & 1) ? -1 : 1) == -d[r])
-                    out->heads[hpre++] = ((b0 + r) << 13) | (((pv >> 1) - 1) << 1) | (d[r] < 0 ? 1 : 0);
-                pv = ((b0 + r + 1) << 1) | (d[r] < 0 ? 1 : 0);
-            }
+        int pv = in;  // previous strict pair as ((index + 1) << 1 | descending)
+        for (unsigned int m = strict; m != 0u; m &= m - 1u) {
+            const int r = __builtin_ctz(m);
+            const int dd = (int)((descm >> r) & 1u);
+            if (pv != 0 && (pv & 1) != dd) out->heads[hpre++] = ((b0 + r) << 13) | (((pv >> 1) - 1) << 1) | dd;
+            pv = ((b0 + r + 1) << 1) | dd;
         }
     }
     if (tid == 0) {
@@ -324,81 +321,99 @@ __device__ void run_plan(Ctl* ctl, int64_t n, int64_t ntiles, const typename C::
         if (tid == 0 && was_runs) ctl->path = SR_PATH_GENERAL;
     };
 
-    // A. entries in array order: each tile's turnings -- the first one
-    //    against the last strict pair of earlier tiles (carried by a
-    //    max-scan) -- and the dense piece starts and ends; counted, then
-    //    written at the prefix offset.  Tiles in contiguous ranges per thread.
-    const int64_t per = (ntiles + NT - 1) / NT;
-    const int64_t t0 = (int64_t)tid * per < ntiles ? (int64_t)tid * per : ntiles;
-    const int64_t t1 = (t0 + per) < ntiles ? (t0 + per) : ntiles;
-    auto lastv = [&](int64_t t) {  // ((index + 1) << 1 | descending) of tile t's last strict pair
-        const RunTile& r = rd[t];
-        return r.lz < 0 ? 0LL : ((((long long)(t * TC + r.lz)) + 1) << 1) | ((r.signs >> 1) & 1);
-    };
-    long long agg = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        const long long v = lastv(t);
-        agg = v > agg ? v : agg;
+    // A. entries in array order, in rounds of NT tiles (one tile per thread,
+    //    coalesced 16-byte descriptor heads): each tile's turnings -- the
+    //    first one against the last strict pair of earlier tiles, carried by a
+    //    max-scan of ((index + 1) << 1 | descending) -- and the dense piece
+    //    starts and ends, written at the running offset (a scan of per-tile
+    //    counts).  Stops as soon as the entries or the dense keys exceed what
+    //    a plan may hold.
+    __shared__ long long s_carry, s_base, s_dk;
+    __shared__ int s_nh[NT + 1];
+    if (tid == 0) {
+        s_carry = 0;
+        s_base = 0;
+        s_dk = 0;
     }
-    long long incl = agg;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const long long y = __shfl_up(incl, o);
-        if (lane >= o) incl = y > incl ? y : incl;
-    }
-    if (lane == kWave - 1) s_w[wave] = incl;
     __syncthreads();
-    long long carry = __shfl_up(incl, 1);
-    if (lane == 0) carry = 0;
-    for (int w = 0; w < wave; ++w) carry = s_w[w] > carry ? s_w[w] : carry;
-
-    long long cnt = 0, dense_keys = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        long long o = 0;
-        if (pass == 1) {
-            long long tot, dk;
-            o = wg_scan_excl(cnt, s_w, tot);
-            (void)wg_scan_excl(dense_keys, s_w, dk);
-            if (tot + 1 > kRunMaxBase || 2 * dk > n) {  // leaves = boundaries + 1
-                reject();
-                return;
-            }
-            if (tid == 0) ra->nbase = tot;  // entries, for now
-            dense_keys = dk;
+    for (int64_t r0 = 0; r0 < ntiles; r0 += NT) {
+        const int64_t t = r0 + tid;
+        const bool have = t < ntiles;
+        const int4 hd = have ? *reinterpret_cast<const int4*>(rd + t) : make_int4(0, -1, -1, 0);
+        const int nh = hd.x, fz = hd.y, lz = hd.z, signs = hd.w;  // RunTile's first four fields
+        s_nh[tid + 1] = nh;
+        if (tid == 0) s_nh[0] = r0 > 0 ? rd[r0 - 1].nh : 0;
+        const long long lv = (have && lz >= 0) ? ((((long long)(t * TC + lz)) + 1) << 1) | ((signs >> 1) & 1) : 0;
+        long long incl = lv;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const long long y = __shfl_up(incl, o);
+            if (lane >= o) incl = y > incl ? y : incl;
         }
-        auto put = [&](long long pos, long long kind, long long j) {
-            if (pass) {
+        if (lane == kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        long long carry = __shfl_up(incl, 1);
+        if (lane == 0) carry = 0;
+        long long rmax = 0;
+        for (int w = 0; w < NT / kWave; ++w) {
+            if (w < wave) carry = s_w[w] > carry ? s_w[w] : carry;
+            rmax = s_w[w] > rmax ? s_w[w] : rmax;
+        }
+        carry = s_carry > carry ? s_carry : carry;
+        const bool pdense = t > 0 && s_nh[tid] < 0;
+        int cnt = 0;
+        long long dk = 0;
+        bool carry_turn = false;
+        if (have) {
+            const int64_t st = t * TC;
+            if (nh < 0) {
+                if (t > 0 && ((t % g) == 0 || !pdense)) ++cnt;
+                dk = ((st + TC) < n ? (st + TC) : n) - st;
+            } else {
+                if (pdense) ++cnt;
+                if (fz >= 0 && carry != 0) {
+                    const int cs = (carry & 1) ? -1 : 1, fs = (signs & 1) ? -1 : 1;
+                    carry_turn = cs == -fs;
+                    if (carry_turn) ++cnt;
+                }
+                cnt += nh;
+            }
+        }
+        long long tot, dtot;
+        long long o = s_base + wg_scan_excl(cnt, s_w, tot);
+        (void)wg_scan_excl(dk, s_w, dtot);
+        if (s_base + tot + 1 > kRunMaxBase || 2 * (s_dk + dtot) > n) {  // leaves = entries + 1
+            reject();
+            return;
+        }
+        if (have) {
+            const int64_t st = t * TC;
+            auto put = [&](long long pos, long long kind, long long j) {
                 ra->ent[o] = pos | (kind << 56);
                 ra->ent_j[o] = j;
                 ++o;
-            } else {
-                ++cnt;
-            }
-        };
-        long long c = carry;
-        for (int64_t t = t0; t < t1; ++t) {
-            const RunTile& r = rd[t];
-            const int nh = r.nh, fz = r.fz;
-            const bool pdense = t > 0 && rd[t - 1].nh < 0;
-            const int64_t s = t * TC;
+            };
             if (nh < 0) {
-                if (t > 0 && ((t % g) == 0 || !pdense)) put(s, 2, 0);
-                if (!pass) dense_keys += ((s + TC) < n ? (s + TC) : n) - s;
+                if (t > 0 && ((t % g) == 0 || !pdense)) put(st, 2, 0);
             } else {
-                if (pdense) put(s, 3, 0);
-                if (fz >= 0 && c != 0) {
-                    const int cs = (c & 1) ? -1 : 1, fs = (r.signs & 1) ? -1 : 1;
-                    if (cs == -fs) put(s + fz, fs < 0 ? 5 : 4, (c >> 1) - 1);
-                }
+                if (pdense) put(st, 3, 0);
+                if (carry_turn) put(st + fz, (signs & 1) ? 5 : 4, (carry >> 1) - 1);
                 for (int h = 0; h < nh; ++h) {
-                    const int v = r.heads[h];
-                    put(s + (v >> 13), (v & 1) ? 5 : 4, s + ((v >> 1) & 0xFFF));
+                    const int v = rd[t].heads[h];
+                    put(st + (v >> 13), (v & 1) ? 5 : 4, st + ((v >> 1) & 0xFFF));
                 }
             }
-            const long long v = lastv(t);
-            if (v != 0) c = v;
         }
+        __syncthreads();
+        if (tid == 0) {
+            s_carry = rmax > s_carry ? rmax : s_carry;
+            s_base += tot;
+            s_dk += dtot;
+        }
+        __syncthreads();
     }
+    const long long dense_keys = s_dk;
+    if (tid == 0) ra->nbase = s_base;  // entries, for now
     __syncthreads();
 
     // B. leaf boundaries: dense markers, and the boundary of each turning
@@ -533,7 +548,7 @@ __device__ void run_plan(Ctl* ctl, int64_t n, int64_t ntiles, const typename C::
     const int np = P + (P & 1);
     const double rcost = (double)(desc_keys + dense_keys) / (double)n + np;
     const double gcost = 1.0 + M;
-    if (np > M || !(rcost < gcost) || !(rcost < ocost)) {
+    if (np > M || !(rcost + 1.0 <= gcost) || !(rcost < ocost)) {  // save at least one pass
         reject();
         return;
     }
@@ -607,6 +622,73 @@ __device__ void runs_reverse(S* keys, const RunArea* ra) {
     }
 }
 
+// Chunk c of RUNS merge pass k: its group (binary search in the pass's chunk
+// prefix) as [a0, mid) + [mid, e), and the chunk's first output inside it.
+struct RunChunk {
+    long long a0, mid, e, out0, first;  // first: index of the group's first chunk
+};
+__device__ __forceinline__ RunChunk run_chunk(const RunArea* ra, int k, long long c, long long CH) {
+    const long long* pre = ra->pre + ra->pbase[k];
+    const long long L = ra->L;
+    const long long G = (L + (2LL << k) - 1) >> (k + 1);
+    long long lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const long long mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const long long l0 = lo << (k + 1);
+    const long long lm = (l0 + (1LL << k)) < L ? (l0 + (1LL << k)) : L;
+    const long long le = (l0 + (2LL << k)) < L ? (l0 + (2LL << k)) : L;
+    RunChunk r;
+    r.a0 = ra->lb[l0];
+    r.mid = ra->lb[lm];
+    r.e = ra->lb[le];
+    r.first = pre[lo];
+    r.out0 = (c - pre[lo]) * CH;
+    return r;
+}
+
+// RUNS merge pass k with co-ranks from the partition launch (co[c] for every
+// chunk c of the pass), persistent and double-buffered like the general pass.
+template <class MC, class S>
+__device__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra, S* U, S* S1, int k,
+                                   const int64_t* co) {
+    if (k >= ra->npasses) return;
+    const long long total = ra->ptotal[k];
+    const S* src = (k & 1) ? S1 : U;
+    S* dst = (k & 1) ? U : S1;
+    long long c = blockIdx.x;
+    if (c >= total) return;
+    typename MC::Win w;
+    RunChunk rc = run_chunk(ra, k, c, MC::CH);
+    MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
+    MC::load(src + rc.a0, nullptr, w);
+    int b = 0;
+    for (;;) {
+        MC::stage(buf[b], w);
+        const int na = w.na, cnt = w.cnt;
+        const long long out0 = w.out0, a0 = rc.a0;
+        __syncthreads();
+        const long long cn = c + gridDim.x;
+        if (cn < total) {
+            rc = run_chunk(ra, k, cn, MC::CH);
+            MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
+            MC::load(src + rc.a0, nullptr, w);
+        }
+        typename MC::U v[MC::ITEMS];
+        uint32_t pv[MC::ITEMS];
+        MC::merge(buf[b], na, cnt, v, pv);
+        __syncthreads();
+        MC::stage_out(buf[b], cnt, v, pv);
+        __syncthreads();
+        MC::store(buf[b], dst + a0, nullptr, out0, cnt);
+        if (cn >= total) break;
+        c = cn;
+        b ^= 1;
+    }
+}
+
 // Merge pass k of the RUNS job: chunks of the pass's groups, grid-stride.
 template <class MC, class S>
 __device__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, int k) {
@@ -667,6 +749,7 @@ struct FewTable {
     unsigned long long cnt[kFewBuckets];      // keys per bucket
     long long off[kFewBuckets + 1];           // first output position of each bucket
     long long bpre[kFewBuckets];              // between keys in earlier buckets
+    unsigned long long sample[kFewSample];    // the probe's sample, sorted in place (raw keys)
 };
 
 template <class U>
@@ -811,13 +894,13 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
                                                   const RunTile* rdesc) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
+    __shared__ typename TS::Smem sm;
     if constexpr (!PAIRS) {
         // RUNS: sort the dense 4096-key tiles of this tile in place, both at
         // once when both are dense (the plan's dense pieces)
-        if (ctl != nullptr && rdesc != nullptr && ld_agent(&ctl->path) == SR_PATH_RUNS) {
+        if (ctl != nullptr && rdesc != nullptr && ctl->path == SR_PATH_RUNS) {
             constexpr int G = TS::T / kClsTC;
             static_assert(G == 1 || G == 2, "tile = 1 or 2 run-scan tiles");
-            __shared__ typename TS::Smem sm;
             const int64_t ncls = (n + kClsTC - 1) / kClsTC;
             const int64_t q0 = (int64_t)blockIdx.x * G;
             const bool d0 = q0 < ncls && rdesc[q0].nh < 0;
@@ -848,7 +931,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
             return;
         }
     }
-    if (ctl != nullptr && ld_agent(&ctl->path) == SR_PATH_REVERSED) {
+    if (ctl != nullptr && ctl->path == SR_PATH_REVERSED) {
         constexpr int H = TS::T / 2;
         constexpr int R = H / WG;
         const int64_t half = n / 2;
@@ -885,7 +968,6 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
     if (!v.active) return;
     const int64_t base = (int64_t)blockIdx.x * TS::T;
     if (base >= v.n) return;
-    __shared__ typename TS::Smem sm;
     const int valid = (int)((v.n - base) < TS::T ? (v.n - base) : TS::T);
     TS::run(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
             valid);
@@ -895,8 +977,20 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
 // output chunk c (c*CH) inside its pair of runs.  One thread per chunk.
 template <class C>
 __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C::S* S1, int64_t n, int M,
-                                                   int64_t T, int k, int CH, int64_t* co, const Ctl* ctl) {
+                                                   int64_t T, int k, int CH, int64_t* co, const Ctl* ctl,
+                                                   const RunArea* ra) {
     using S = typename C::S;
+    if (ra != nullptr && ctl != nullptr && ctl->path == SR_PATH_RUNS) {
+        // RUNS: co-rank of every chunk of the pass inside its leaf group
+        if (k >= ra->npasses) return;
+        const S* src = (k & 1) ? S1 : U;
+        const long long total = ra->ptotal[k];
+        for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < total; c += (long long)gridDim.x * 256) {
+            const RunChunk rc = run_chunk(ra, k, c, CH);
+            co[c] = corank_thread<C>(src + rc.a0, rc.mid - rc.a0, src + rc.mid, rc.e - rc.mid, rc.out0);
+        }
+        return;
+    }
     const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k);
     if (!v.active) return;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -927,13 +1021,13 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
     static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
     if constexpr (!PAIRS) {
         if (ctl != nullptr) {
-            const int path = ld_agent(&ctl->path);
+            const int path = ctl->path;
             if (ra != nullptr && path == SR_PATH_RUNS) {
                 runs_merge<MC, S>(sm, ra, U, S1, k);
                 return;
             }
-            if (ft != nullptr && path == SR_PATH_FEW && k == ld_agent(&ctl->job_passes)) {
-                few_place<C, WG>(U, S1 + (n - (int64_t)ld_agent(&ctl->m)), n, ft, &sm);
+            if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
+                few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
             }
         }
@@ -962,13 +1056,13 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
     static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
     if constexpr (!PAIRS) {
         if (ctl != nullptr) {
-            const int path = ld_agent(&ctl->path);
+            const int path = ctl->path;
             if (ra != nullptr && path == SR_PATH_RUNS) {
-                runs_merge<MC, S>(sm.c, ra, U, S1, k);
+                runs_merge_persist<MC, S>(sm.p.b, ra, U, S1, k, co);
                 return;
             }
-            if (ft != nullptr && path == SR_PATH_FEW && k == ld_agent(&ctl->job_passes)) {
-                few_place<C, WG>(U, S1 + (n - (int64_t)ld_agent(&ctl->m)), n, ft, &sm);
+            if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
+                few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
             }
         }
@@ -1002,22 +1096,21 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
                                                      int runs_ok, RunTile* rdesc, FewTable* ft,
                                                      typename C::S* s1) {
     using U = typename C::U;
-    const int path = ld_agent(&ctl->path);
+    const int path = ctl->path;
     if (path == SR_PATH_FEW) {
         const int64_t f0 = (int64_t)blockIdx.x * kClsTC;
         const int64_t f1 = (f0 + kClsTC) < n ? (f0 + kClsTC) : n;
         few_count<C>(keys, n, f0, f1, ctl, ft, s1);
         return;
     }
-    const bool do_runs = runs_ok && (path == SR_PATH_RUNS || path == SR_PATH_OUTLIER);
+    const bool do_runs = runs_ok && (path == SR_PATH_RUNS || (path == SR_PATH_OUTLIER && ctl->dual));
     if (path != SR_PATH_OUTLIER && !do_runs) return;
     __shared__ U sk[kClsW];
-    __shared__ uint16_t dx[kClsW];  // dense list of kept keys: window index of the q-th kept key
-    __shared__ uint8_t kp[kClsW];
+    __shared__ uint8_t kp[kClsW];                     // kept flags after the rounds
+    __shared__ unsigned int kw[kClsWG], rw[kClsWG];   // per-thread kept masks, removals by others
     __shared__ int wtot[kClsWG / kWave];
     __shared__ int s_flag[2];
     __shared__ U s_first, s_last;
-    __shared__ int s_kc;
     const int tid = threadIdx.x;
     const int lane = (int)__lane_id();
     const int wave = tid / kWave;
@@ -1049,99 +1142,105 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     if (do_runs) runscan_lds<U>(sk, n, c0, c1, w0, rdesc + t);
     if (path != SR_PATH_OUTLIER) return;
 
-    bool converged = false;
+    // Removal rounds on a register copy: thread tid owns window positions
+    // bj .. bj+16 (bit r of km: position bj + r still kept) and their keys.
+    // In a round every kept key q is compared with the next kept key j; at a
+    // descent the larger key goes if dropping it restores the order with the
+    // previous kept key, else the smaller if that restores it with the kept
+    // key after j, else both.  Neighbours come from register sweeps over the
+    // thread's own positions and, across its ends, from the kept masks the
+    // threads publish in LDS (kw); a removal of a position another thread
+    // owns goes to that thread's word rw by an LDS atomic OR.  All decisions
+    // of a round use the masks of the previous round, so the result does not
+    // depend on thread timing.  A round without removals means the kept keys
+    // are sorted.
     const int bj = tid * kClsPer;
-    {
-        // Fast path: the first removal round on the raw window (every key is
-        // still kept, so no compaction is needed), then a check of each kept
-        // key against the next kept key.  Only a tile with a descent left
-        // goes through the compacting rounds below.
-        bool rem = false;
+    U key[kClsPer];
+    unsigned int km = 0u;
 #pragma unroll
-        for (int r = 0; r < kClsPer; ++r) {
-            const int q = bj + r;
-            if (q + 1 < wn && sk[q] > sk[q + 1]) {
-                bool ra = q == 0 || sk[q - 1] <= sk[q + 1];
-                bool rb = !ra && (q + 2 >= wn || sk[q] <= sk[q + 2]);
-                if (!ra && !rb) ra = rb = true;
-                if (ra) kp[q] = 0;
-                if (rb) kp[q + 1] = 0;
-                rem = true;
+    for (int r = 0; r < kClsPer; ++r) {
+        key[r] = sk[bj + r];  // positions >= wn are never kept
+        km |= (bj + r < wn ? 1u : 0u) << r;
+    }
+    rw[tid] = 0u;
+    const int uend = (wn + kClsPer - 1) / kClsPer;  // threads owning window positions
+    bool converged = false;
+    for (int iter = 0; iter <= kClsMaxIter; ++iter) {
+        kw[tid] = km;
+        __syncthreads();
+        int r1 = -1, r2 = -1;  // first two kept positions after this thread's
+        for (int u = tid + 1; km != 0u && u < uend && r2 < 0; ++u) {
+            unsigned int w = kw[u];
+            while (w != 0u && r2 < 0) {
+                const int pos = u * kClsPer + __builtin_ctz(w);
+                w &= w - 1u;
+                if (r1 < 0) r1 = pos;
+                else r2 = pos;
             }
         }
-        if (rem) s_flag[0] = 1;
-        __syncthreads();
-        if (s_flag[0] == 0) {
-            converged = true;
-        } else {
-            bool desc = false;
+        int l1 = -1;  // last kept position before this thread's
+        for (int u = tid - 1; km != 0u && u >= 0 && l1 < 0; --u) {
+            const unsigned int w = kw[u];
+            if (w != 0u) l1 = u * kClsPer + 31 - __builtin_clz(w);
+        }
+        // backward sweep: the next two kept keys after each own position
+        U n1k[kClsPer], n2k[kClsPer];
+        {
+            U k1 = r1 >= 0 ? sk[r1] : (U)0, k2 = r2 >= 0 ? sk[r2] : (U)0;
 #pragma unroll
-            for (int r = 0; r < kClsPer; ++r) {
-                const int q = bj + r;
-                if (q < wn && kp[q]) {
-                    int j = q + 1;
-                    while (j < wn && !kp[j]) ++j;
-                    if (j < wn && sk[q] > sk[j]) desc = true;
+            for (int r = kClsPer - 1; r >= 0; --r) {
+                n1k[r] = k1;
+                n2k[r] = k2;
+                if ((km >> r) & 1u) {
+                    k2 = k1;
+                    k1 = key[r];
                 }
             }
-            if (desc) s_flag[1] = 1;
-            __syncthreads();
-            converged = s_flag[1] == 0;
         }
-        __syncthreads();
-        if (tid < 2) s_flag[tid] = 0;
-        __syncthreads();
-    }
-    for (int iter = 0; !converged && iter < kClsMaxIter; ++iter) {
-        // dense list of the kept keys (block-wide exclusive scan of kp)
-        int pre[kClsPer];
-        int loc = 0;
-#pragma unroll
-        for (int r = 0; r < kClsPer; ++r) {
-            pre[r] = loc;
-            loc += kp[bj + r];
-        }
-        int x = loc;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int y = __shfl_up(x, d);
-            if (lane >= d) x += y;
-        }
-        if (lane == kWave - 1) wtot[wave] = x;
-        __syncthreads();
-        int off = x - loc, cnt = 0;
-#pragma unroll
-        for (int w = 0; w < kClsWG / kWave; ++w) {
-            cnt += wtot[w];
-            if (w < wave) off += wtot[w];
-        }
-#pragma unroll
-        for (int r = 0; r < kClsPer; ++r) {
-            if (kp[bj + r]) dx[off + pre[r]] = (uint16_t)(bj + r);
-        }
-        __syncthreads();
+        // forward sweep with the previous kept key: the removals
+        unsigned int own_rem = 0u;
         bool rem = false;
+        {
+            bool hp = l1 >= 0;
+            U pk = hp ? sk[l1] : (U)0;
 #pragma unroll
-        for (int r = 0; r < kClsPer; ++r) {
-            const int q = bj + r;
-            if (q + 1 < cnt && sk[dx[q]] > sk[dx[q + 1]]) {
-                bool ra = q == 0 || sk[dx[q - 1]] <= sk[dx[q + 1]];
-                bool rb = !ra && (q + 2 >= cnt || sk[dx[q]] <= sk[dx[q + 2]]);
-                if (!ra && !rb) ra = rb = true;
-                if (ra) kp[dx[q]] = 0;
-                if (rb) kp[dx[q + 1]] = 0;
-                rem = true;
+            for (int r = 0; r < kClsPer; ++r) {
+                if ((km >> r) & 1u) {
+                    const unsigned int above = r + 1 < kClsPer ? km >> (r + 1) : 0u;
+                    const int na = __builtin_popcount(above);
+                    const bool h1 = na >= 1 || r1 >= 0;
+                    const bool h2 = na >= 2 || (na == 1 && r1 >= 0) || r2 >= 0;
+                    if (h1 && key[r] > n1k[r]) {
+                        bool ra = !hp || pk <= n1k[r];
+                        bool rb = !ra && (!h2 || key[r] <= n2k[r]);
+                        if (!ra && !rb) ra = rb = true;
+                        if (ra) own_rem |= 1u << r;
+                        if (rb) {
+                            if (na >= 1) own_rem |= 1u << (r + 1 + __builtin_ctz(above));
+                            else atomicOr(&rw[r1 / kClsPer], 1u << (r1 % kClsPer));
+                        }
+                        rem = true;
+                    }
+                    pk = key[r];
+                    hp = true;
+                }
             }
         }
         if (rem) s_flag[iter & 1] = 1;
         __syncthreads();
         const bool any = s_flag[iter & 1] != 0;
         if (tid == 0) s_flag[(iter + 1) & 1] = 0;
+        km &= ~(own_rem | rw[tid]);
+        rw[tid] = 0u;
         if (!any) {
             converged = true;
             break;
         }
     }
+    // the kept flags as bytes for the core pass below
+#pragma unroll
+    for (int r = 0; r < kClsPer; ++r) kp[bj + r] = (unsigned char)((km >> r) & 1u);
+    __syncthreads();
 
     // the tile's core [c0, c1): kept ranks, first and last kept key
     const int cs = (int)(c0 - w0), ce = (int)(c1 - w0);
@@ -1217,7 +1316,7 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
     constexpr int CP = kClsTC / kClsWG;
     constexpr int NW = kClsTC / 32;  // mask words per tile
     static_assert(NW <= kClsWG, "one word per thread in the scan");
-    const int path = ld_agent(&ctl->path);
+    const int path = ctl->path;
     if (path == SR_PATH_RUNS && ra != nullptr) {
         runs_reverse<S>(keys, ra);
         return;
@@ -1289,99 +1388,114 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
                                                    unsigned long long* kpref_t, int64_t T_sort,
                                                    const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
                                                    int runs_ok, int64_t merge_ch, int M, FewTable* ft) {
-    const int path0 = ld_agent(&ctl->path);
+    const int path0 = ctl->path;
     if (path0 == SR_PATH_FEW) {
         few_plan(ctl, n, ft, T_sort);
         return;
     }
-    const bool want_runs =
-        runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->force_path != SR_PATH_OUTLIER));
+    const bool want_runs = runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->dual));
     __shared__ double s_ocost;
     if (path0 == SR_PATH_OUTLIER) verify_outliers(ctl, n, ntiles, tfirst, tlast, tcount, kpref_t, T_sort, &s_ocost);
     else if (path0 == SR_PATH_RUNS && threadIdx.x == 0) s_ocost = 1e300;
     __syncthreads();
-    if (want_runs) run_plan<C>(ctl, n, ntiles, keys, rdesc, ra, (int)(T_sort / kClsTC), merge_ch, M, s_ocost,
-                               path0 == SR_PATH_RUNS);
+    // a run plan cannot beat an outlier job of about two passes
+    if (want_runs && s_ocost > 2.5)
+        run_plan<C>(ctl, n, ntiles, keys, rdesc, ra, (int)(T_sort / kClsTC), merge_ch, M, s_ocost,
+                    path0 == SR_PATH_RUNS);
 }
 
 __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
                                 const unsigned long long* tlast, const unsigned long long* tcount,
                                 unsigned long long* kpref_t, int64_t T_sort, double* ocost) {
-    __shared__ unsigned long long s_last[kVerWG];
-    __shared__ int s_has[kVerWG];
-    __shared__ unsigned long long s_kept[kVerWG / kWave];
-    __shared__ int s_bad;
+    // Rounds of kVerWG x 4 consecutive tiles (each thread four consecutive
+    // ones, so the loads of a wavefront share cache lines): the kept prefix
+    // continues a running base, and each tile's first kept key is checked
+    // against the last kept key of the nearest earlier tile that kept any
+    // (in this thread, in an earlier thread of the round -- a max-scan of
+    // thread indices -- or in an earlier round).
+    constexpr int Q = 4;
+    __shared__ long long s_w[kVerWG / kWave];
+    __shared__ unsigned long long s_lastk[kVerWG];
+    __shared__ unsigned long long s_base, s_carry_key;
+    __shared__ int s_carry_has, s_bad;
     const int tid = threadIdx.x;
-    if (tid == 0) s_bad = 0;
-    const int64_t per = (ntiles + kVerWG - 1) / kVerWG;
-    const int64_t t0 = (int64_t)tid * per;
-    const int64_t t1 = (t0 + per) < ntiles ? (t0 + per) : ntiles;
-    // own chunk: joins inside it, kept total, last kept key
-    unsigned long long kept = 0, last = 0;
-    bool has = false, bad = false;
-    unsigned long long first_of_chunk = 0;
-    bool chunk_first_set = false;
-    for (int64_t tb = t0; tb < t1; tb += 8) {
-        unsigned long long cv[8], fv[8], lv[8];
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    if (tid == 0) {
+        s_bad = 0;
+        s_base = 0;
+        s_carry_has = 0;
+        s_carry_key = 0;
+    }
+    __syncthreads();
+    for (int64_t r0 = 0; r0 < ntiles; r0 += (int64_t)kVerWG * Q) {
+        const int64_t tb = r0 + (int64_t)tid * Q;
+        unsigned long long cv[Q], fv[Q], lv[Q];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t t = tb + q;
-            cv[q] = t < t1 ? tcount[t] : 0ull;
-            fv[q] = t < t1 ? tfirst[t] : 0ull;
-            lv[q] = t < t1 ? tlast[t] : 0ull;
+        for (int q = 0; q < Q; ++q) {
+            const bool ok = tb + q < ntiles;
+            cv[q] = ok ? tcount[tb + q] : 0ull;
+            fv[q] = ok ? tfirst[tb + q] : 0ull;
+            lv[q] = ok ? tlast[tb + q] : 0ull;
         }
+        unsigned long long kept = 0, last = 0, first = 0;
+        bool has = false, bad = false;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < Q; ++q) {
             if (cv[q] == 0) continue;
             if (has && fv[q] < last) bad = true;
-            if (!chunk_first_set) {
-                chunk_first_set = true;
-                first_of_chunk = fv[q];
-            }
+            if (!has) first = fv[q];
             has = true;
             last = lv[q];
             kept += cv[q];
         }
-    }
-    s_last[tid] = last;
-    s_has[tid] = has ? 1 : 0;
-    // exclusive prefix of the kept counts over the chunks (wave scan + waves)
-    const int lane = (int)__lane_id();
-    unsigned long long xs = kept;
+        long long tot;
+        long long pre = wg_scan_excl((long long)kept, s_w, tot) + (long long)s_base;
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const unsigned long long y = __shfl_up(xs, d);
-        if (lane >= d) xs += y;
-    }
-    if (lane == kWave - 1) s_kept[tid / kWave] = xs;
-    __syncthreads();
-    unsigned long long pre = xs - kept;
-    for (int q = 0; q < tid / kWave; ++q) pre += s_kept[q];
-    for (int64_t tb = t0; tb < t1; tb += 8) {
-        unsigned long long cv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) cv[q] = tb + q < t1 ? tcount[tb + q] : 0ull;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (tb + q < t1) kpref_t[tb + q] = pre;
-            pre += cv[q];
+        for (int q = 0; q < Q; ++q) {
+            if (tb + q < ntiles) kpref_t[tb + q] = (unsigned long long)pre;
+            pre += (long long)cv[q];
         }
-    }
-    // join with the nearest earlier chunk that kept any key
-    if (chunk_first_set) {
-        for (int u = tid - 1; u >= 0; --u) {
-            if (s_has[u]) {
-                if (first_of_chunk < s_last[u]) bad = true;
-                break;
+        // nearest earlier thread of this round that kept any key
+        s_lastk[tid] = last;
+        int hi = has ? tid : -1;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(hi, o);
+            if (lane >= o) hi = y > hi ? y : hi;
+        }
+        __syncthreads();
+        if (lane == kWave - 1) s_w[wave] = hi;
+        __syncthreads();
+        int prev = __shfl_up(hi, 1);
+        if (lane == 0) prev = -1;
+        int rmax = -1;
+        for (int w = 0; w < kVerWG / kWave; ++w) {
+            const int v = (int)s_w[w];
+            if (w < wave) prev = v > prev ? v : prev;
+            rmax = v > rmax ? v : rmax;
+        }
+        if (has) {
+            if (prev >= 0) {
+                if (first < s_lastk[prev]) bad = true;
+            } else if (s_carry_has && first < s_carry_key) {
+                bad = true;
             }
         }
+        if (bad) s_bad = 1;
+        __syncthreads();
+        if (tid == 0) {
+            s_base += (unsigned long long)tot;
+            if (rmax >= 0) {
+                s_carry_has = 1;
+                s_carry_key = s_lastk[rmax];
+            }
+        }
+        __syncthreads();
     }
-    if (bad) s_bad = 1;
-    __syncthreads();
     if (tid == 0) {
-        unsigned long long total = 0;
-        for (int w = 0; w < kVerWG / kWave; ++w) total += s_kept[w];
-        const bool fail = s_bad != 0 || ld_agent(&ctl->bad_join) != 0 || total > (unsigned long long)n;
+        const unsigned long long total = s_base;
+        const bool fail = s_bad != 0 || ctl->bad_join != 0 || total > (unsigned long long)n;
         const int64_t m = n - (int64_t)total;
         if (fail || m > n / 2) {
             ctl->path = SR_PATH_GENERAL;
@@ -1546,7 +1660,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             for (int q = 0; q < 4; ++q) red[q][wave] = acc[q];
         __syncthreads();
     }
-    __shared__ int s_path, s_force;
+    __shared__ int s_path, s_force, s_dual;
     __shared__ unsigned long long s_desc, s_asc;
     if (last && tid == 0) {
         unsigned long long tot[4] = {0, 0, 0, 0};
@@ -1576,6 +1690,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                      ? -((runs_ok && sturn * 64 <= spairs) ? SR_PATH_RUNS : SR_PATH_GENERAL) - 10
                      : path;
         s_force = force == SR_PATH_FEW;
+        s_dual = path == SR_PATH_OUTLIER && runs_ok && force != SR_PATH_OUTLIER && sturn * 64 <= spairs;
         s_desc = desc;
         s_asc = asc;
     }
@@ -1584,34 +1699,29 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         int path = s_path;
         if (path == SR_PATH_FEW || path <= -10) {
             // FEW: the distinct keys of kFewSample evenly spread samples,
-            // sorted in LDS (bitonic), become the splitters if there are at
-            // most kFewMax of them (or, when forced, the first kFewMax)
-            __shared__ U fs[kFewSample];
+            // sorted by the tile sorter (256 threads x 4 keys) in a scratch
+            // row of the table, become the splitters if there are at most
+            // kFewMax of them (or, when forced, the first kFewMax)
+            using FS = TileSort<C, kProbeWG, kFewSample / kProbeWG, false>;
+            static_assert(FS::T == kFewSample, "one sample tile");
+            __shared__ typename FS::Smem fsm;
             __shared__ int s_cnt[kProbeWG / kWave];
-            for (int i = tid; i < kFewSample; i += kProbeWG) fs[i] = C::enc(keys[(int64_t)i * n / kFewSample]);
+            S* samp = reinterpret_cast<S*>(ft->sample);
+            for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[(int64_t)i * n / kFewSample];
             __syncthreads();
-            for (int k = 2; k <= kFewSample; k <<= 1) {
-                for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int i = tid; i < kFewSample / 2; i += kProbeWG) {
-                        const int lo = 2 * i - (i & (j - 1));
-                        const int hi = lo + j;
-                        const bool up = (lo & k) == 0;
-                        const U a = fs[lo], b = fs[hi];
-                        if ((a > b) == up) {
-                            fs[lo] = b;
-                            fs[hi] = a;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
+            FS::run(fsm, samp, samp, nullptr, nullptr, kFewSample);
+            __syncthreads();
             constexpr int PER = kFewSample / kProbeWG;
             int c = 0;
             bool first[PER];
+            U cur[PER];
+            U prv = tid > 0 ? C::enc(samp[tid * PER - 1]) : (U)0;
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
                 const int i = tid * PER + r;
-                first[r] = i == 0 || fs[i] != fs[i - 1];
+                cur[r] = C::enc(samp[i]);
+                first[r] = i == 0 || cur[r] != prv;
+                prv = cur[r];
                 c += first[r] ? 1 : 0;
             }
             int xc = c;
@@ -1631,7 +1741,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             if (take) {
 #pragma unroll
                 for (int r = 0; r < PER; ++r)
-                    if (first[r] && pre < kFewMax) ft->split[pre++] = (unsigned long long)fs[tid * PER + r];
+                    if (first[r] && pre < kFewMax) ft->split[pre++] = (unsigned long long)cur[r];
                 const int ns = total < kFewMax ? total : kFewMax;
                 for (int b = tid; b < 2 * ns + 1; b += kProbeWG) ft->cnt[b] = 0;
                 if (tid == 0) ft->ns = (unsigned long long)ns;
@@ -1642,6 +1752,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         }
         if (tid == 0) {
             ctl->path = path;
+            ctl->dual = s_dual;
             ctl->reserved[0] = s_desc;  // kept for sr_last_stats
             ctl->reserved[1] = s_asc;
             ctl->reserved[2] = 0;
@@ -2200,7 +2311,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     const bool few_ok = !PAIRS && g_few_enabled;
     const bool scan_ok = outlier_ok || runs_ok || few_ok;
     const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
-    const size_t co_bytes = round_up((size_t)(nchunks + 2) * 8, 256);
+    // co-ranks of a merge pass; a RUNS pass has up to one extra chunk per leaf group
+    const size_t co_bytes = round_up((size_t)(nchunks + 2 + kRunMaxLeaves) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
     const size_t cls_arr = round_up((size_t)ncls * 8, 256);
     Workspace* ws = nullptr;
@@ -2289,7 +2401,7 @@ tile_done:
             {
                 ProfScope ps(ls, "partition");
                 hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, ls, keys, skeys,
-                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl);
+                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea);
                 SR_LAUNCH_CHECK("partition");
             }
             ProfScope ps(ls, "merge");

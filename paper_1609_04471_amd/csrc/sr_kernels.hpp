@@ -199,6 +199,7 @@ struct MergeChunk {
     using S = typename C::S;
     using U = typename C::U;
     static constexpr int CH = WG * IT;
+    static constexpr int ITEMS = IT;
     static constexpr int VN = 16 / sizeof(S);
     static constexpr int PADDED = CH + CH / 16;
     static_assert(WG >= 2 * kWave, "two wavefronts search the window bounds");
@@ -469,7 +470,7 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
     PassView<S> v{};
     v.active = false;
     v.split = -1;
-    const int path = ld_agent(&ctl->path);
+    const int path = ctl->path;
     if (path == 3 /* SR_PATH_GENERAL */) {
         const int from = (M - k) & 1;
         v.src = from ? S1 : U;
@@ -480,8 +481,8 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
         v.width = T << k;
         v.active = true;
     } else if (path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW: slot P is its fill pass */) {
-        const int64_t m = (int64_t)ld_agent(&ctl->m);
-        const int P = ld_agent(&ctl->job_passes);
+        const int64_t m = (int64_t)ctl->m;
+        const int P = ctl->job_passes;
         S* X0 = S1 + (n - m);
         if (k < P) {
             const int from = (P - k) & 1;
@@ -517,7 +518,7 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         v.active = true;
         return v;
     }
-    const int path = ld_agent(&ctl->path);
+    const int path = ctl->path;
     if (path == 3 /* SR_PATH_GENERAL */) {
         v.src = U;
         v.dst = (M & 1) ? S1 : U;
@@ -526,8 +527,8 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         v.n = n;
         v.active = true;
     } else if (path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW */) {
-        const int64_t m = (int64_t)ld_agent(&ctl->m);
-        const int P = ld_agent(&ctl->job_passes);
+        const int64_t m = (int64_t)ctl->m;
+        const int P = ctl->job_passes;
         S* X0 = S1 + (n - m);
         v.src = X0;
         v.dst = (P & 1) ? U : X0;

@@ -167,3 +167,27 @@ def test_runs_switch_off(gpu):
     finally:
         gpu.set_option("runs_path", 1)
     assert check(gpu, a)["path"] == "runs"
+
+
+@pytest.mark.parametrize("name,k", [("even_teeth", 8), ("equal_teeth", 64), ("even_teeth", 3)])
+def test_runs_with_partition_launch(gpu, name, k):
+    """Above 2^22 keys the leaf merges take their co-ranks from the partition
+    launch and run persistent and double-buffered."""
+    n = 5_000_011
+    a = inputs.class_int32(name, n, k, seed=k)
+    st = check(gpu, a)
+    assert st["path"] == "runs" and st["merge_passes"] >= 2, st
+
+
+def test_runs_random_mix_large(gpu):
+    rng = np.random.default_rng(11)
+    parts = []
+    total = 0
+    while total < 6_000_000:
+        ln = int(rng.integers(50_000, 900_000))
+        x = np.cumsum(rng.integers(0, 3, size=ln)) + int(rng.integers(-2**30, 2**30))
+        parts.append(x[::-1] if rng.random() < 0.5 else x)
+        total += ln
+    a = np.concatenate(parts).astype(np.int32)
+    st = check(gpu, a)
+    assert st["path"] == "runs", st
