@@ -254,22 +254,8 @@ __device__ __forceinline__ void wave_sort(E (&v)[N]) {
 // ------------------------------------------------------- Merge Path search
 // co-rank of diagonal d between sorted A[0, la) and B[0, lb): the number i of
 // A elements among the first d outputs of the stable merge.  A[i] precedes
-// B[d-1-i] when A[i] <= B[d-1-i].
-template <class U>
-__device__ __forceinline__ int corank_lds(const U* A, int la, const U* B, int lb, int d) {
-    int lo = d > lb ? d - lb : 0;
-    int hi = d < la ? d : la;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (A[mid] <= B[d - 1 - mid])
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// The same search by a single thread in global memory (plain binary search).
+// B[d-1-i] when A[i] <= B[d-1-i].  By a single thread in global memory
+// (plain binary search).
 template <class C>
 __device__ __forceinline__ int64_t corank_thread(const typename C::S* A, int64_t la,
                                                  const typename C::S* B, int64_t lb, int64_t d) {

@@ -46,9 +46,14 @@ struct TileSort {
     static_assert(IT % VN == 0, "IT must hold whole 16-byte vectors");
     static_assert(WG % kWave == 0, "whole wavefronts");
 
+    // LDS rows are padded by one word per 32 (pad): the per-thread runs of
+    // IT consecutive elements (put) and the 16-byte output reads then hit
+    // the banks at most twice per wavefront access instead of IT times.
+    static constexpr int TP = T + T / 32;
+    static __device__ __forceinline__ int pad(int e) { return e + (e >> 5); }
     struct Smem {
-        U k[T];
-        uint32_t p[PAIRS ? T : 1];     // tile position of each element
+        U k[TP];
+        uint32_t p[PAIRS ? TP : 1];    // tile position of each element
         uint32_t pay[PAIRS ? T : 1];   // payload, by tile position
     };
 
@@ -74,21 +79,20 @@ struct TileSort {
         const int out0 = tid * IT;
         const int gs = out0 & ~(2 * width - 1);
         const int d = out0 - gs;
-        const U* A = sm.k + gs;
-        const U* B = A + width;
         int lo = d > width ? d - width : 0;
         int hi = d < width ? d : width;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
+            const int xa = pad(gs + mid), xb = pad(gs + width + d - 1 - mid);
             bool a_first;
-            if constexpr (PAIRS) a_first = !before(B[d - 1 - mid], sm.p[gs + width + d - 1 - mid], A[mid], sm.p[gs + mid]);
-            else a_first = A[mid] <= B[d - 1 - mid];
+            if constexpr (PAIRS) a_first = !before(sm.k[xb], sm.p[xb], sm.k[xa], sm.p[xa]);
+            else a_first = sm.k[xa] <= sm.k[xb];
             if (a_first) lo = mid + 1;
             else hi = mid;
         }
         int i = lo, j = d - lo;
-        int ia = gs + (i < width ? i : width - 1);
-        int ib = gs + width + (j < width ? j : width - 1);
+        int ia = pad(gs + (i < width ? i : width - 1));
+        int ib = pad(gs + width + (j < width ? j : width - 1));
         U a = sm.k[ia], b = sm.k[ib];
         uint32_t pa = 0, pb = 0;
         if constexpr (PAIRS) {
@@ -102,7 +106,7 @@ struct TileSort {
             else v[r] = ta ? a : b;
             i += ta ? 1 : 0;
             j += ta ? 0 : 1;
-            const int nx = ta ? gs + (i < width ? i : width - 1) : gs + width + (j < width ? j : width - 1);
+            const int nx = pad(ta ? gs + (i < width ? i : width - 1) : gs + width + (j < width ? j : width - 1));
             const U kn = sm.k[nx];
             a = ta ? kn : a;
             b = ta ? b : kn;
@@ -117,11 +121,12 @@ struct TileSort {
     static __device__ __forceinline__ void put(Smem& sm, int tid, const E (&v)[IT]) {
 #pragma unroll
         for (int r = 0; r < IT; ++r) {
+            const int x = pad(tid * IT + r);
             if constexpr (PAIRS) {
-                sm.k[tid * IT + r] = v[r].k;
-                sm.p[tid * IT + r] = v[r].p;
+                sm.k[x] = v[r].k;
+                sm.p[x] = v[r].p;
             } else {
-                sm.k[tid * IT + r] = v[r];
+                sm.k[x] = v[r];
             }
         }
     }
@@ -173,14 +178,14 @@ struct TileSort {
                 const int e0 = (tid + q * WG) * VN;
                 V16<S> x;
 #pragma unroll
-                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[e0 + j]);
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[pad(e0 + j)]);
                 reinterpret_cast<V16<S>*>(dst)[tid + q * WG] = x;
             }
         } else {
-            for (int e = tid; e < valid; e += WG) dst[e] = C::dec(sm.k[e]);
+            for (int e = tid; e < valid; e += WG) dst[e] = C::dec(sm.k[pad(e)]);
         }
         if constexpr (PAIRS) {
-            for (int e = tid; e < valid; e += WG) pdst[e] = sm.pay[sm.p[e]];
+            for (int e = tid; e < valid; e += WG) pdst[e] = sm.pay[sm.p[pad(e)]];
         }
     }
 };
@@ -310,7 +315,18 @@ struct MergeChunk {
         const int t0 = threadIdx.x * IT;
         if (t0 >= cnt) return;
         const int nb = cnt - na;
-        int i = corank_lds(b.k, na, b.k + na, nb, t0);
+        int i;
+        {
+            // co-rank of t0 between the staged A = [0, na) and B = [na, cnt)
+            int lo = t0 > nb ? t0 - nb : 0;
+            int hi = t0 < na ? t0 : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (b.k[mid] <= b.k[na + t0 - 1 - mid]) lo = mid + 1;
+                else hi = mid;
+            }
+            i = lo;
+        }
         int j = t0 - i;
         const int last = cnt - 1;
         int ia = i < na ? i : last;
