@@ -2085,7 +2085,10 @@ hipEvent_t get_event() {
         return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;  // this launch goes unprofiled
+    }
     return e;
 }
 
@@ -2099,14 +2102,25 @@ struct ProfScope {
             std::lock_guard<std::mutex> lk(g_mu);
             a = get_event();
             b = get_event();
-            hipEventRecord(a, st);
+            if (a == nullptr || b == nullptr || hipEventRecord(a, st) != hipSuccess) {
+                (void)hipGetLastError();
+                if (a) g_event_pool.push_back(a);
+                if (b) g_event_pool.push_back(b);
+                a = b = nullptr;
+            }
         }
     }
     ~ProfScope() {
         if (a) {
-            hipEventRecord(b, st);
+            const bool ok = hipEventRecord(b, st) == hipSuccess;
             std::lock_guard<std::mutex> lk(g_mu);
-            g_prof.push_back(ProfRec{name, a, b});
+            if (ok) {
+                g_prof.push_back(ProfRec{name, a, b});
+            } else {
+                (void)hipGetLastError();
+                g_event_pool.push_back(a);
+                g_event_pool.push_back(b);
+            }
         }
     }
 };
@@ -2173,7 +2187,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
     if (ws->hdr == nullptr) {
         e = hipMalloc(&ws->hdr, kHdrBytes);
         if (e != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             return fail(SR_ERR_OUT_OF_MEMORY, "workspace header allocation failed");
         }
         ws->ctl = reinterpret_cast<Ctl*>(ws->hdr);
@@ -2189,7 +2203,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         if (ws->base) {
             e = hipStreamSynchronize(st);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            hipFree(ws->base);
+            (void)hipFree(ws->base);
             ws->base = nullptr;
             ws->bytes = 0;
         }
@@ -2197,7 +2211,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         ws->generation++;
         e = hipMalloc(&ws->base, alloc);
         if (e != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             return fail(SR_ERR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(alloc) + " bytes failed");
         }
         ws->bytes = alloc;
@@ -2206,7 +2220,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         if (ws->aux) {
             e = hipStreamSynchronize(st);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            hipFree(ws->aux);
+            (void)hipFree(ws->aux);
             ws->aux = nullptr;
             ws->aux_bytes = 0;
         }
@@ -2214,7 +2228,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         const size_t alloc = round_up(std::max(aux_bytes, (size_t)1 << 16), 4096);
         e = hipMalloc(&ws->aux, alloc);
         if (e != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             return fail(SR_ERR_OUT_OF_MEMORY, "look-back allocation of " + std::to_string(alloc) + " bytes failed");
         }
         ws->aux_bytes = alloc;
@@ -2247,13 +2261,13 @@ int64_t resident_blocks(K kernel, int threads) {
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, int64_t> cache;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int cus = 0, per_cu = 0;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t r = (int64_t)std::max(cus, 1) * per_cu;
@@ -2542,7 +2556,7 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
     std::memset(&key, 0, sizeof(key));
     key.kind = kind;
     key.dt = dt;
-    hipGetDevice(&key.dev);
+    (void)hipGetDevice(&key.dev);
     key.keys = keys;
     key.pay = pay;
     key.off = off;
@@ -2592,12 +2606,12 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
             g_profile = prof;
         }
         if (s != SR_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return s;
         }
         if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
         std::lock_guard<std::mutex> lk(g_mu);
         g_graphs[key] = exec;
@@ -2756,7 +2770,7 @@ sr_status sr_release_stream(void* stream) {
     g_err.clear();
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     Workspace* ws = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -2767,7 +2781,7 @@ sr_status sr_release_stream(void* stream) {
         g_last.erase(st);
         for (auto gi = g_graphs.begin(); gi != g_graphs.end();) {
             if (gi->first.st == st && gi->first.dev == dev) {
-                hipGraphExecDestroy(gi->second);
+                (void)hipGraphExecDestroy(gi->second);
                 gi = g_graphs.erase(gi);
             } else {
                 ++gi;
@@ -2775,9 +2789,9 @@ sr_status sr_release_stream(void* stream) {
         }
     }
     hipError_t e = hipStreamSynchronize(st);
-    if (ws->hdr) hipFree(ws->hdr);
-    if (ws->base) hipFree(ws->base);
-    if (ws->aux) hipFree(ws->aux);
+    if (ws->hdr) (void)hipFree(ws->hdr);
+    if (ws->base) (void)hipFree(ws->base);
+    if (ws->aux) (void)hipFree(ws->aux);
     delete ws;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return SR_OK;
@@ -2817,8 +2831,16 @@ sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nse
     g_err.clear();
     const int es = elem_bytes(dt);
     if (es == 0 || !bytes) return fail(SR_ERR_INVALID_ARGUMENT, "bad argument");
-    size_t b = kHdrBytes + round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
-    b += round_up((n / 1024 + 2) * 8, 256) + 4 * round_up((n / 4096 + 1) * 8, 256) + round_up(n / 8 + 512, 256);
+    // upper bound of what sort_impl / seg_impl allocate, over every tuning:
+    // header; co-ranks (smallest merge chunk 2048, plus one per run leaf
+    // group); the partner array (keys, payload); outlier / run-scan tile
+    // arrays per 4096 keys (4 words, a 512-byte kept mask, a RunTile) and the
+    // run plan; segment plan arrays
+    const size_t ncls = n / kClsTC + 1;
+    size_t b = kHdrBytes + round_up((n / 2048 + 2 + kRunMaxLeaves) * 8, 256);
+    b += round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
+    b += 4 * round_up(ncls * 8, 256) + round_up(ncls * (kClsTC / 8), 256);
+    b += round_up(ncls * sizeof(RunTile), 256) + round_up(sizeof(RunArea), 256);
     b += round_up((nseg + 1) * 8 * 4, 256);
     *bytes = std::max(b, (size_t)1 << 20);
     return SR_OK;

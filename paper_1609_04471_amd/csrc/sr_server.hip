@@ -85,8 +85,6 @@ struct sr_server {
 };
 
 void sr_server::loop() {
-    int dev = 0;
-    hipGetDevice(&dev);
     while (!stop.load()) {
         bool progress = false;
         std::unique_lock<std::mutex> lk(mu);
@@ -130,17 +128,30 @@ void sr_server::loop() {
             }
             lk.unlock();
             sr_status s;
+            std::string msg;
             if (sl.reqs.size() == 1) {
                 s = sr_sort_keys(dt, sl.h_ptrs[0], (size_t)sl.h_lens[0], sl.st);
+            } else if (hipMemcpyAsync(sl.d_ptrs, sl.h_ptrs, sizeof(void*) * sl.reqs.size(), hipMemcpyHostToDevice,
+                                      sl.st) != hipSuccess ||
+                       hipMemcpyAsync(sl.d_lens, sl.h_lens, sizeof(int64_t) * sl.reqs.size(), hipMemcpyHostToDevice,
+                                      sl.st) != hipSuccess) {
+                s = SR_ERR_DEVICE;
+                msg = std::string("staging the batch: ") + hipGetErrorString(hipGetLastError());
             } else {
-                hipMemcpyAsync(sl.d_ptrs, sl.h_ptrs, sizeof(void*) * sl.reqs.size(), hipMemcpyHostToDevice, sl.st);
-                hipMemcpyAsync(sl.d_lens, sl.h_lens, sizeof(int64_t) * sl.reqs.size(), hipMemcpyHostToDevice, sl.st);
                 s = sr_sort_batch(dt, sl.d_ptrs, sl.d_lens, sl.reqs.size(), keys, sl.st);
             }
-            hipEventRecord(sl.done, sl.st);
+            if (s != SR_OK && msg.empty()) msg = sr_last_error_message();
+            // the completion event is recorded even after a failed enqueue, so
+            // the batch still finishes (with its error status)
+            if (hipEventRecord(sl.done, sl.st) != hipSuccess) {
+                msg = std::string("completion event: ") + hipGetErrorString(hipGetLastError());
+                s = SR_ERR_DEVICE;
+                (void)hipStreamSynchronize(sl.st);  // an event never recorded again reads as complete
+                (void)hipGetLastError();
+            }
             lk.lock();
             for (size_t q : sl.reqs) reqs[q].status = s;
-            if (s != SR_OK && error.empty()) error = sr_last_error_message();
+            if (s != SR_OK && error.empty()) error = msg;
             sl.busy = true;
             progress = true;
         }
@@ -182,7 +193,7 @@ sr_status sr_server_create(const sr_server_config* cfg, sr_server** out) {
             hipHostMalloc((void**)&sl.h_lens, sizeof(int64_t) * cfg->max_batch_requests, 0) != hipSuccess ||
             hipMalloc((void**)&sl.d_ptrs, sizeof(void*) * cfg->max_batch_requests) != hipSuccess ||
             hipMalloc((void**)&sl.d_lens, sizeof(int64_t) * cfg->max_batch_requests) != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             sr_server_destroy(s);
             return SR_ERR_OUT_OF_MEMORY;
         }
@@ -193,7 +204,11 @@ sr_status sr_server_create(const sr_server_config* cfg, sr_server** out) {
                 return SR_ERR_OUT_OF_MEMORY;
             }
         }
-        hipStreamSynchronize(sl.st);
+        if (hipStreamSynchronize(sl.st) != hipSuccess) {
+            (void)hipGetLastError();
+            sr_server_destroy(s);
+            return SR_ERR_DEVICE;
+        }
     }
     s->worker = std::thread([s]() { s->loop(); });
     *out = s;
@@ -257,15 +272,16 @@ sr_status sr_server_destroy(sr_server* s) {
     s->stop.store(true);
     if (s->worker.joinable()) s->worker.join();
     for (auto& sl : s->slots) {
-        if (sl.st) hipStreamSynchronize(sl.st);
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.h_ptrs) hipHostFree(sl.h_ptrs);
-        if (sl.h_lens) hipHostFree(sl.h_lens);
-        if (sl.d_ptrs) hipFree(sl.d_ptrs);
-        if (sl.d_lens) hipFree(sl.d_lens);
+        // teardown: failures here leave nothing to recover
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.h_ptrs) (void)hipHostFree(sl.h_ptrs);
+        if (sl.h_lens) (void)hipHostFree(sl.h_lens);
+        if (sl.d_ptrs) (void)hipFree(sl.d_ptrs);
+        if (sl.d_lens) (void)hipFree(sl.d_lens);
         if (sl.st) {
             sr_release_stream(sl.st);
-            hipStreamDestroy(sl.st);
+            (void)hipStreamDestroy(sl.st);
         }
     }
     delete s;
