@@ -652,7 +652,7 @@ __device__ __forceinline__ RunChunk run_chunk(const RunArea* ra, int k, long lon
 // RUNS merge pass k with co-ranks from the partition launch (co[c] for every
 // chunk c of the pass), persistent and double-buffered like the general pass.
 template <class MC, class S>
-__device__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra, S* U, S* S1, int k,
+__device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra, S* U, S* S1, int k,
                                    const int64_t* co) {
     if (k >= ra->npasses) return;
     const long long total = ra->ptotal[k];
@@ -691,7 +691,7 @@ __device__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra
 
 // Merge pass k of the RUNS job: chunks of the pass's groups, grid-stride.
 template <class MC, class S>
-__device__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, int k) {
+__device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, int k) {
     if (k >= ra->npasses) return;
     const long long total = ra->ptotal[k];
     const long long* pre = ra->pre + ra->pbase[k];
@@ -836,7 +836,7 @@ __device__ void few_plan(Ctl* ctl, int64_t n, FewTable* ft, int64_t T_sort) {
 // WG x 8 outputs; lds holds the table (at least 8 * (2 * kFewBuckets + 1) +
 // 8 * kFewMax bytes).
 template <class C, int WG>
-__device__ void few_place(typename C::S* U, const typename C::S* X0, int64_t n, const FewTable* ft, void* lds) {
+__device__ __forceinline__ void few_place(typename C::S* U, const typename C::S* X0, int64_t n, const FewTable* ft, void* lds) {
     using S = typename C::S;
     constexpr int IT = 8;
     long long* off = static_cast<long long*>(lds);
@@ -1041,7 +1041,9 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
 
 // Merge slot k, persistent double-buffered, co-ranks from k_partition.
 // RUNS passes reuse its LDS for one-chunk merges with in-kernel co-ranks.
-template <class C, int WG, int IT, bool PAIRS>
+// NT: nontemporal window loads and output stores (arrays far beyond the
+// caches; keeps the partition launch's searches cached).
+template <class C, int WG, int IT, bool PAIRS, bool NT = false>
 __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
                                                       const int64_t* co, const Ctl* ctl, const RunArea* ra,
@@ -1069,7 +1071,7 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
     }
     const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
     if (!v.active) return;
-    MP::run(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
+    MP::template run<NT>(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
 }
 
 // --------------------------------------------------------------- outliers
@@ -2419,7 +2421,10 @@ tile_done:
                 SR_LAUNCH_CHECK("partition");
             }
             ProfScope ps(ls, "merge");
-            auto kern = k_merge_persist<C, TN::MWG, TN::MIT, PAIRS>;
+            // nontemporal from 128 MB of keys on: two such arrays exceed the MALL
+            const bool nt = (size_t)n * sizeof(S) >= ((size_t)1 << 27);
+            auto kern = nt ? k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, true>
+                           : k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, false>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
                                (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
@@ -3023,7 +3028,10 @@ sr_status sr_copy_bandwidth_probe(void* dst, const void* src, size_t bytes, void
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 == 0) return SR_OK;
     ProfScope ps((hipStream_t)stream, "copy16");
-    const unsigned g = (unsigned)std::min<int64_t>(cdiv(n16, 256 * 4), 65536);
+    // one 16-byte element per thread over the whole range: the fastest copy
+    // shape measured on MI355X (grid-stride grids of 1K-64K workgroups are
+    // 8-25 % slower)
+    const unsigned g = (unsigned)std::min<int64_t>(cdiv(n16, 256), (int64_t)1 << 30);
     hipLaunchKernelGGL(k_copy16, dim3(g), dim3(256), 0, (hipStream_t)stream, (uint4*)dst, (const uint4*)src, n16);
     SR_LAUNCH_CHECK("copy16");
     return SR_OK;

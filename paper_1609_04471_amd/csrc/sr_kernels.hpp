@@ -285,6 +285,9 @@ struct MergeChunk {
     }
 
     // Issue every window load of this thread (they stay in flight until stage()).
+    // NT: nontemporal loads and stores, for arrays far larger than the caches
+    // (the pass's data is not read again before the next pass).
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const S* src, const uint32_t* psrc, Win& w) {
         const int tid = threadIdx.x;
 #pragma unroll
@@ -292,8 +295,13 @@ struct MergeChunk {
             const int e = tid + r * WG;
             if (e < w.cnt) {
                 const int64_t gi = e < w.na ? w.gA + e : w.gB + (e - w.na);
-                w.x[r] = src[gi];
-                if constexpr (PAIRS) w.px[r] = psrc[gi];
+                if constexpr (NT) {
+                    w.x[r] = __builtin_nontemporal_load(src + gi);
+                    if constexpr (PAIRS) w.px[r] = __builtin_nontemporal_load(psrc + gi);
+                } else {
+                    w.x[r] = src[gi];
+                    if constexpr (PAIRS) w.px[r] = psrc[gi];
+                }
             }
         }
     }
@@ -360,6 +368,7 @@ struct MergeChunk {
         }
     }
 
+    template <bool NT = false>
     static __device__ __forceinline__ void store(const Buf& b, S* dst, uint32_t* pdst, int64_t out0, int cnt) {
         const int tid = threadIdx.x;
         S* out = dst + out0;
@@ -370,7 +379,13 @@ struct MergeChunk {
                 V16<S> x;
 #pragma unroll
                 for (int j = 0; j < VN; ++j) x.v[j] = C::dec(b.k[pad(e0 + j)]);
-                reinterpret_cast<V16<S>*>(out)[tid + q * WG] = x;
+                if constexpr (NT) {
+                    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+                    __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(&x),
+                                                reinterpret_cast<v4u*>(out) + tid + q * WG);
+                } else {
+                    reinterpret_cast<V16<S>*>(out)[tid + q * WG] = x;
+                }
             }
         } else {
             for (int e = tid; e < cnt; e += WG) out[e] = C::dec(b.k[pad(e)]);
@@ -428,14 +443,15 @@ struct MergePersistent {
         typename MC::Buf b[2];
     };
 
-    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
-                               int64_t n, int64_t width, int64_t split, const int64_t* co) {
+    template <bool NT = false>
+    static __device__ __forceinline__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
+                                               int64_t n, int64_t width, int64_t split, const int64_t* co) {
         const int64_t nchunks = (n + CH - 1) / CH;
         int64_t c = blockIdx.x;
         if (c >= nchunks) return;
         typename MC::Win w;
         MC::window_from_co(n, width, split, c * CH, co, w);
-        MC::load(src, psrc, w);
+        MC::template load<NT>(src, psrc, w);
         int buf = 0;
         for (;;) {
             MC::stage(sm.b[buf], w);
@@ -445,7 +461,7 @@ struct MergePersistent {
             const int64_t cn = c + gridDim.x;
             if (cn < nchunks) {
                 MC::window_from_co(n, width, split, cn * CH, co, w);
-                MC::load(src, psrc, w);
+                MC::template load<NT>(src, psrc, w);
             }
             U v[IT];
             uint32_t pv[IT];
@@ -453,7 +469,7 @@ struct MergePersistent {
             __syncthreads();
             MC::stage_out(sm.b[buf], cnt, v, pv);
             __syncthreads();
-            MC::store(sm.b[buf], dst, pdst, out0, cnt);
+            MC::template store<NT>(sm.b[buf], dst, pdst, out0, cnt);
             if (cn >= nchunks) break;
             c = cn;
             buf ^= 1;
