@@ -741,12 +741,14 @@ __device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea*
 constexpr int kFewMax = 64;
 constexpr int kFewBuckets = 2 * kFewMax + 1;
 constexpr int kFewSample = 1024;
+constexpr int kFewCopies = 32;  // bucket counter copies (workgroup w adds to copy w % 32)
 constexpr size_t kFewLdsBytes = 8 * (2 * kFewBuckets + 1) + 8 * kFewMax;  // few_place's table copy
 
 struct FewTable {
     unsigned long long ns;                    // splitters
     unsigned long long split[kFewMax];        // encoded, ascending, distinct
-    unsigned long long cnt[kFewBuckets];      // keys per bucket
+    unsigned long long cnt[kFewCopies][kFewBuckets];  // keys per bucket, spread over copies
+    unsigned long long tot[kFewBuckets];      // keys per bucket
     long long off[kFewBuckets + 1];           // first output position of each bucket
     long long bpre[kFewBuckets];              // between keys in earlier buckets
     unsigned long long sample[kFewSample];    // the probe's sample, sorted in place (raw keys)
@@ -806,21 +808,31 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
         }
     }
     __syncthreads();
+    unsigned long long* cc = ft->cnt[blockIdx.x % kFewCopies];
     for (int b = tid; b < nb; b += kClsWG)
-        if (hist[b] != 0u) atomicAdd(&ft->cnt[b], (unsigned long long)hist[b]);
+        if (hist[b] != 0u) atomicAdd(&cc[b], (unsigned long long)hist[b]);
 }
 
-// Bucket offsets and the job (thread 0 of the verify workgroup).
+// Bucket totals (the counter copies summed, one bucket per thread), then
+// offsets and the job (thread 0 of the verify workgroup).
 __device__ void few_plan(Ctl* ctl, int64_t n, FewTable* ft, int64_t T_sort) {
+    __shared__ unsigned long long s_tot[kFewBuckets];
+    const int nb = 2 * (int)ft->ns + 1;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        unsigned long long t = 0;
+        for (int c = 0; c < kFewCopies; ++c) t += ft->cnt[c][b];
+        s_tot[b] = t;
+        ft->tot[b] = t;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     const unsigned long long m = ctl->m;
-    const int nb = 2 * (int)ft->ns + 1;
     long long o = 0, bp = 0;
     for (int b = 0; b < nb; ++b) {
         ft->off[b] = o;
         ft->bpre[b] = bp;
-        o += (long long)ft->cnt[b];
-        if ((b & 1) == 0) bp += (long long)ft->cnt[b];
+        o += (long long)s_tot[b];
+        if ((b & 1) == 0) bp += (long long)s_tot[b];
     }
     ft->off[nb] = o;
     if (o != n || (unsigned long long)bp != m || 4 * m > (unsigned long long)n) {
@@ -1745,7 +1757,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                 for (int r = 0; r < PER; ++r)
                     if (first[r] && pre < kFewMax) ft->split[pre++] = (unsigned long long)cur[r];
                 const int ns = total < kFewMax ? total : kFewMax;
-                for (int b = tid; b < 2 * ns + 1; b += kProbeWG) ft->cnt[b] = 0;
+                for (int b = tid; b < kFewCopies * (2 * ns + 1); b += kProbeWG)
+                    ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)] = 0;
                 if (tid == 0) ft->ns = (unsigned long long)ns;
                 path = SR_PATH_FEW;
             } else {
@@ -2157,7 +2170,7 @@ std::map<hipStream_t, LastCall> g_last;
 
 // Workspace header: control block, then the probe's per-workgroup slots.
 constexpr size_t kCtlBytes = 256;
-constexpr size_t kHdrBytes = 64 * 1024;
+constexpr size_t kHdrBytes = 128 * 1024;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
 static_assert(kCtlBytes + kProbeMaxGrid * 4 * 8 + (kProbeMaxGrid / kProbeGroup + 1) * 256 <= kHdrBytes,
               "probe slots and group counters");
