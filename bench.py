@@ -76,9 +76,10 @@ def main():
     ap.add_argument("--no-seg", action="store_true", help="skip the batched-segments section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-classes", action="store_true", help="skip the Sec. 2 presorted-class section")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 2^20 keys and 2^24 pairs section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve",
-                                       "classes"],
+                                       "classes", "configs"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -237,6 +238,12 @@ def main():
         torch.cuda.synchronize()
     result.update(per_type_256M=per_big or None, roofline=roofline, copy_GBps=round(copy_gbps, 1) if copy_gbps else None)
 
+    # ------------------------------------------------------------ 2^20 keys, 2^24 pairs
+    cfgs = None
+    if not args.no_configs and args.only in (None, "configs"):
+        cfgs = configs_section(torch, np, inputs, sortrace, dev, stream)
+    result["configs"] = cfgs
+
     # ------------------------------------------------------------ Sec. 2 classes
     classes = None
     if not args.no_classes and args.only in (None, "classes"):
@@ -345,10 +352,62 @@ def main():
         "copy_GBps": result.get("copy_GBps"),
         "segmented_4096": result.get("segmented"),
         "presorted_classes": result.get("classes"),
+        "keys_2p20_and_pairs_2p24": result.get("configs"),
         "serving": result.get("serving"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def configs_section(torch, np, inputs, sortrace, dev, stream):
+    """2^20 uniform int32 keys, and 2^24 stable (uint64 key in geometric runs
+    with 10% equal steps, uint32 payload = index) pairs: Mkeys/s, path,
+    passes; the pairs output is checked for sortedness and stability."""
+    def timed(fn, restore, reps):
+        out = []
+        for i in range(reps + 2):
+            restore()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            if i >= 2:
+                out.append(a.elapsed_time(b))
+        return statistics.median(out)
+
+    res = {}
+    n1 = 1 << 20
+    src = torch.from_numpy(inputs.random_int32(n1, inputs.seed_for(1, 0, n1))).to(dev)
+    work = torch.empty_like(src)
+    ms = timed(lambda: sortrace.sort_keys(work), lambda: work.copy_(src), 20)
+    st = sortrace.last_stats()
+    assert bool((work[1:] >= work[:-1]).all())
+    res["int32_random_2p20"] = {"ms_median": round(ms, 5), "Mkeys_s": round(n1 / (ms / 1e3) / 1e6, 1),
+                                "path": st["path"], "passes": st["passes"]}
+    log(f"2^20 keys: {res['int32_random_2p20']}")
+    n3 = 1 << 24
+    hk, hp = inputs.runs_uint64(n3, seed=inputs.seed_for(3, 0, n3))
+    ks = torch.from_numpy(hk.view(np.int64)).to(dev)
+    ps = torch.from_numpy(hp.view(np.int32)).to(dev)
+    kw, pw = torch.empty_like(ks), torch.empty_like(ps)
+
+    def restore():
+        kw.copy_(ks)
+        pw.copy_(ps)
+    ms = timed(lambda: sortrace.sort_pairs(kw, pw, dtype="uint64"), restore, 10)
+    st = sortrace.last_stats()
+    gk = kw.cpu().numpy().view(np.uint64)
+    gp = pw.cpu().numpy().view(np.uint32)
+    ok = bool(np.all(gk[1:] >= gk[:-1])) and bool(np.all((gk[1:] != gk[:-1]) | (gp[1:] > gp[:-1])))
+    ok = ok and bool(np.array_equal(gk, hk[gp]))
+    res["uint64_pairs_runs_2p24"] = {"ms_median": round(ms, 4), "Mpairs_s": round(n3 / (ms / 1e3) / 1e6, 1),
+                                     "path": st["path"], "passes": st["passes"],
+                                     "algorithmic_GBps": round(st["bytes_moved"] / (ms / 1e3) / 1e9, 1),
+                                     "stable_and_sorted": ok}
+    log(f"2^24 pairs: {res['uint64_pairs_runs_2p24']}")
+    assert ok
+    return res
 
 
 def classes_section(args, torch, np, inputs, sortrace, dev, stream):
