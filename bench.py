@@ -41,11 +41,17 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
+    """Hash of the device code: the two device headers and the kernel half of
+    sr_engine.hip (everything before its host-side marker)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1609_04471_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("sr_device.hpp", "sr_kernels.hpp"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    eng = open(os.path.join(csrc, "sr_engine.hip"), "rb").read()
+    cut = eng.find(b"\n// Host side\n")
+    if cut < 0:
+        raise RuntimeError("sr_engine.hip has lost its host-side marker")
+    h.update(eng[:cut])
     return h.hexdigest()[:16]
 
 
@@ -110,30 +116,47 @@ def main():
         log("generating 2M inputs")
         pristine = {k: torch.from_numpy(host_input(k, N_SMALL)).to(dev) for k in types}
         total_steps = args.warmup + args.steps
-        bufs = [{k: pristine[k].clone() for k in types} for _ in range(total_steps)]
-        torch.cuda.synchronize()
-        for s in range(args.warmup):
+
+        def time_steps():
+            """(gpu ms, wall s) of args.steps timed steps after the warmup."""
+            bufs = [{k: pristine[k].clone() for k in types} for _ in range(total_steps)]
+            torch.cuda.synchronize()
+            for s in range(args.warmup):
+                for k in types:
+                    sortrace.sort_keys(bufs[s][k])
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record(stream)
+            for s in range(args.warmup, total_steps):
+                for k in types:
+                    sortrace.sort_keys(bufs[s][k])
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            # correctness of the timed outputs (cheap property: nondecreasing)
             for k in types:
-                sortrace.sort_keys(bufs[s][k])
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        for s in range(args.warmup, total_steps):
-            for k in types:
-                sortrace.sort_keys(bufs[s][k])
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gpu_ms = ev0.elapsed_time(ev1)
+                b = bufs[-1][k]
+                assert bool((b[1:] >= b[:-1]).all()), k
+            return ev0.elapsed_time(ev1), wall
+
+        gpu_ms, wall = time_steps()
         ms_per_step = gpu_ms / args.steps
         value = args.steps * len(types) * N_SMALL / (gpu_ms / 1e3) / 1e6
         log(f"step: {ms_per_step:.4f} ms (wall {wall * 1e3 / args.steps:.4f} ms) -> {value:.1f} Mkeys/s")
-        # correctness of the timed outputs (cheap property: nondecreasing)
-        for k in types:
-            b = bufs[-1][k]
-            assert bool((b[1:] >= b[:-1]).all()), k
-        del bufs
+        table = sortrace.tune_get()
+        tuning = {"table": os.path.relpath(os.environ.get("SR_TUNE_TABLE", sortrace.TUNE_TABLE), ROOT)
+                  if table else None, "rows": len(table)}
+        if table:
+            # the same step under the built-in launch-shape rules, for comparison
+            sortrace.tune_set([])
+            try:
+                b_ms, _ = time_steps()
+            finally:
+                sortrace.tune_set(table)
+            tuning["step_ms_builtin_rules"] = round(b_ms / args.steps, 5)
+            log(f"step under the built-in shape rules: {b_ms / args.steps:.4f} ms")
+        result["tuning"] = tuning
 
         per_small = {}
         for k in types:
@@ -354,6 +377,7 @@ def main():
         "presorted_classes": result.get("classes"),
         "keys_2p20_and_pairs_2p24": result.get("configs"),
         "serving": result.get("serving"),
+        "tuning": result.get("tuning"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

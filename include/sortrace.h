@@ -224,17 +224,57 @@ const char *sr_last_error_message(void);
  *                 the device, so new data and new offsets in the same buffers
  *                 are handled); 0 = plain launches (default).  sr_sort_keys /
  *                 sr_sort_pairs always launch directly.
+ * The four launch-shape options below default to "auto": the matching row
+ * of the tuning table (sr_tune_set) decides, else the built-in rule given
+ * with each.  A value set here overrides the table for every sort.
  *   "tile_variant" 32-bit keys only: 0 = tile sort by 512 threads x 16 keys,
- *                 1 = 1024 threads x 8 keys (same 8192-key tile), -1 = 1
- *                 below partition_min_n and 0 from it on (default).
- *   "merge_items"  32-bit keys only, merge passes below partition_min_n:
- *                 outputs per thread, 8 (default) or 16.
+ *                 1 = 1024 threads x 8 keys (same 8192-key tile), -1 = auto
+ *                 (built-in: 1 without a partition launch, else 0).
+ *   "merge_items"  32-bit keys only, merge passes without a partition
+ *                 launch: outputs per thread, 8 or 16; 0 = auto (built-in:
+ *                 16 from n = 2^21 on, else 8).
  *   "partition_min_n"  from this n on, every merge pass is preceded by a
- *                 separate Merge Path partition launch; below it each merge
- *                 workgroup searches its own window bounds (default 2^22).
+ *                 separate Merge Path partition launch and merged by a
+ *                 persistent grid; below it each merge workgroup searches
+ *                 its own window bounds.  -1 = auto (built-in 2^23).
+ *   "merge_nontemporal"  persistent merge passes load their windows and
+ *                 store their output with nontemporal hints: 1 = on, 0 = off,
+ *                 -1 = auto (built-in: on for keys-only sorts from 256 MiB
+ *                 of keys, for uint64 pairs from 128 MiB of keys, never for
+ *                 32-bit pairs).
  * Returns SR_ERR_INVALID_ARGUMENT for an unknown name or value.
  */
 sr_status sr_set_option(const char *name, int64_t value);
+
+/*
+ * Tuning table: launch shapes per key type, keys-only or pairs, and size
+ * band, as written by the package's autotuner (a sweep of these fields over
+ * timed sorts on the device).  A sort of n keys uses the row of its dtype and
+ * kind with the largest min_n <= n; a field left at its "unset" value, or a
+ * sort no row matches, takes the built-in rule of the option of the same
+ * name (sr_set_option).  Fields that do not apply to a key type (tile_variant
+ * and merge_items for uint64 keys and for pairs) are ignored.
+ */
+typedef struct {
+    int32_t dtype;         /* sr_dtype */
+    int32_t pairs;         /* 0 = sr_sort_keys, 1 = sr_sort_pairs */
+    int64_t min_n;         /* the band starts here (>= 0) */
+    int32_t tile_variant;  /* 0 or 1; -1 = unset */
+    int32_t merge_items;   /* 8 or 16; 0 = unset */
+    int32_t partition;     /* 1 = separate partition launch, 0 = fused search; -1 = unset */
+    int32_t nontemporal;   /* 1 or 0; -1 = unset */
+} sr_tune_entry;
+
+/* Replaces the process-wide tuning table with `count` rows copied from host
+ * memory (count 0 clears it; entries may then be NULL).  Rows are validated
+ * first: a bad dtype, a negative min_n, a field outside its values, or two
+ * rows with the same (dtype, pairs, min_n) return SR_ERR_INVALID_ARGUMENT and
+ * leave the table unchanged.  At most 1024 rows. */
+sr_status sr_tune_set(const sr_tune_entry *entries, int64_t count);
+
+/* Copies up to `cap` rows of the table (sorted by dtype, pairs, min_n) to
+ * host memory and stores the row count in *count. */
+sr_status sr_tune_get(sr_tune_entry *out, int64_t cap, int64_t *count);
 
 /*
  * With "profile" on: sums the device time of the recorded launches whose

@@ -2079,12 +2079,62 @@ sr_status hip_fail(hipError_t e, const char* what) {
 std::mutex g_mu;
 int g_force_path = -1;
 bool g_profile = false;
-int64_t g_partition_min_n = (int64_t)1 << 22;  // separate Merge Path partition launch from this n on
-bool g_outlier_enabled = true;
-bool g_runs_enabled = true;                      // allow the RUNS path for keys-only sorts
-bool g_few_enabled = true;                       // allow the FEW path for keys-only sorts                   // allow the OUTLIER path for keys-only sorts
-int g_tile_variant = -1;  // -1 auto (1024 x 8 below partition_min_n), 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
-int g_merge_items = 8;    // fused merge: outputs per thread (16 or 8, 32-bit keys only)
+bool g_outlier_enabled = true;  // allow the OUTLIER path for keys-only sorts
+bool g_runs_enabled = true;     // allow the RUNS path for keys-only sorts
+bool g_few_enabled = true;      // allow the FEW path for keys-only sorts
+// Launch-shape options; the "auto" value defers to the tuning table, then to
+// the built-in rule in resolve_shape.
+int64_t g_partition_min_n = -1;  // separate Merge Path partition launch from this n on
+int g_tile_variant = -1;         // 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
+int g_merge_items = 0;           // fused merge: outputs per thread, 8 or 16 (32-bit keys only)
+int g_nontemporal = -1;          // persistent merge: nontemporal window loads and stores
+std::vector<sr_tune_entry> g_tune;  // sorted by (dtype, pairs, min_n)
+
+// Built-in rules, from a sweep of random keys of each type on gfx950.
+constexpr int64_t kPartitionMinN = (int64_t)1 << 23;
+constexpr int64_t kMerge16MinN = (int64_t)1 << 21;     // fused merge: 16 outputs per thread from here
+constexpr size_t kNontemporalBytes = (size_t)1 << 28;  // of keys: two such arrays exceed the MALL
+constexpr int64_t kTuneMaxRows = 1024;
+
+// sr_dtype of a codec
+template <class C>
+struct DtypeOf;
+template <>
+struct DtypeOf<CodecI32> { static constexpr int value = SR_INT32; };
+template <>
+struct DtypeOf<CodecU64> { static constexpr int value = SR_UINT64; };
+template <>
+struct DtypeOf<CodecF32> { static constexpr int value = SR_FLOAT32; };
+
+struct LaunchShape {
+    bool partition;    // separate partition launch + persistent merge
+    int tile_variant;  // 0: TWG x TIT, 1: 1024 x 8 (32-bit keys)
+    int merge_items;   // fused merge outputs per thread (32-bit keys)
+    bool nt;           // nontemporal persistent merge
+};
+
+// Explicit options first, then the table row of (dt, pairs) with the largest
+// min_n <= n, then the built-in rules.  Caller holds g_mu.
+LaunchShape resolve_shape(int dt, bool pairs, int64_t n, size_t key_bytes) {
+    const sr_tune_entry* row = nullptr;
+    for (const sr_tune_entry& e : g_tune)
+        if (e.dtype == dt && e.pairs == (pairs ? 1 : 0) && e.min_n <= n) row = &e;
+    LaunchShape sh;
+    if (g_partition_min_n >= 0) sh.partition = n >= g_partition_min_n;
+    else if (row && row->partition >= 0) sh.partition = row->partition != 0;
+    else sh.partition = n >= kPartitionMinN;
+    if (g_tile_variant >= 0) sh.tile_variant = g_tile_variant;
+    else if (row && row->tile_variant >= 0) sh.tile_variant = row->tile_variant;
+    else sh.tile_variant = sh.partition ? 0 : 1;
+    if (g_merge_items > 0) sh.merge_items = g_merge_items;
+    else if (row && row->merge_items > 0) sh.merge_items = row->merge_items;
+    else sh.merge_items = n >= kMerge16MinN ? 16 : 8;
+    if (g_nontemporal >= 0) sh.nt = g_nontemporal != 0;
+    else if (row && row->nontemporal >= 0) sh.nt = row->nontemporal != 0;
+    else if (!pairs) sh.nt = (size_t)n * key_bytes >= kNontemporalBytes;
+    else sh.nt = key_bytes == 8 && (size_t)n * key_bytes >= kNontemporalBytes / 2;  // not for 32-bit pairs
+    return sh;
+}
 
 struct ProfRec {
     std::string name;
@@ -2358,8 +2408,13 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     int64_t* co = reinterpret_cast<int64_t*>(wd);
     S* skeys = reinterpret_cast<S*>(wd + co_bytes);
     uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes) : nullptr;
-    const bool use_partition = n >= g_partition_min_n;
-    const bool merge8 = sizeof(S) == 4 && !PAIRS && TN::MIT == 16 && g_merge_items == 8;
+    LaunchShape sh;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sh = resolve_shape(DtypeOf<C>::value, PAIRS, n, sizeof(S));
+    }
+    const bool use_partition = sh.partition;
+    const bool merge8 = sizeof(S) == 4 && !PAIRS && TN::MIT == 16 && sh.merge_items == 8;
     const int64_t merge_ch = use_partition ? CH : (merge8 ? (int64_t)TN::MWG * 8 : CH);
     RunTile* rdesc = nullptr;
     RunArea* rarea = nullptr;
@@ -2406,7 +2461,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         // GENERAL / OUTLIER: tile sort of the job; REVERSED: in-place reversal
         ProfScope ps(ls, "tile_sort");
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
-            if (g_tile_variant == 1 || (g_tile_variant == -1 && !use_partition)) {
+            if (sh.tile_variant == 1) {
                 hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
                                    skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc);
                 SR_LAUNCH_CHECK("tile_sort");
@@ -2434,9 +2489,7 @@ tile_done:
                 SR_LAUNCH_CHECK("partition");
             }
             ProfScope ps(ls, "merge");
-            // nontemporal from 128 MB of keys on: two such arrays exceed the MALL
-            const bool nt = (size_t)n * sizeof(S) >= ((size_t)1 << 27);
-            auto kern = nt ? k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, true>
+            auto kern = sh.nt ? k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, true>
                            : k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, false>;
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
@@ -2588,6 +2641,7 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
         key.opts[2] = g_outlier_enabled;
         key.opts[3] = g_tile_variant;
         key.opts[4] = g_merge_items;
+        key.opts[5] = g_nontemporal;
         auto it = g_ws.find({key.dev, st});
         key.gen = it != g_ws.end() && it->second ? it->second->generation : 0;
     }
@@ -2954,7 +3008,7 @@ sr_status sr_set_option(const char* name, int64_t value) {
         return SR_OK;
     }
     if (std::strcmp(name, "partition_min_n") == 0) {
-        if (value < 0) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= 0");
+        if (value < -1) return fail(SR_ERR_INVALID_ARGUMENT, "partition_min_n >= -1");
         g_partition_min_n = value;
         return SR_OK;
     }
@@ -2969,8 +3023,14 @@ sr_status sr_set_option(const char* name, int64_t value) {
         return SR_OK;
     }
     if (std::strcmp(name, "merge_items") == 0) {
-        if (value != 8 && value != 16) return fail(SR_ERR_INVALID_ARGUMENT, "merge_items is 8 or 16");
+        if (value != 0 && value != 8 && value != 16)
+            return fail(SR_ERR_INVALID_ARGUMENT, "merge_items is 0, 8 or 16");
         g_merge_items = (int)value;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "merge_nontemporal") == 0) {
+        if (value < -1 || value > 1) return fail(SR_ERR_INVALID_ARGUMENT, "merge_nontemporal is -1, 0 or 1");
+        g_nontemporal = (int)value;
         return SR_OK;
     }
     if (std::strcmp(name, "outlier_path") == 0) {
@@ -2994,6 +3054,49 @@ sr_status sr_set_option(const char* name, int64_t value) {
         return SR_OK;
     }
     return fail(SR_ERR_INVALID_ARGUMENT, std::string("unknown option ") + name);
+}
+
+sr_status sr_tune_set(const sr_tune_entry* entries, int64_t count) {
+    g_err.clear();
+    if (count < 0 || count > kTuneMaxRows) return fail(SR_ERR_INVALID_ARGUMENT, "count is 0..1024");
+    if (count > 0 && !entries) return fail(SR_ERR_INVALID_ARGUMENT, "entries is NULL");
+    std::vector<sr_tune_entry> rows(entries, entries + count);
+    for (int64_t i = 0; i < count; ++i) {
+        const sr_tune_entry& e = rows[(size_t)i];
+        const std::string at = "tuning row " + std::to_string(i) + ": ";
+        if (e.dtype < SR_INT32 || e.dtype > SR_FLOAT32) return fail(SR_ERR_INVALID_ARGUMENT, at + "bad dtype");
+        if (e.pairs != 0 && e.pairs != 1) return fail(SR_ERR_INVALID_ARGUMENT, at + "pairs is 0 or 1");
+        if (e.min_n < 0) return fail(SR_ERR_INVALID_ARGUMENT, at + "min_n < 0");
+        if (e.tile_variant < -1 || e.tile_variant > 1)
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "tile_variant is -1, 0 or 1");
+        if (e.merge_items != 0 && e.merge_items != 8 && e.merge_items != 16)
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "merge_items is 0, 8 or 16");
+        if (e.partition < -1 || e.partition > 1) return fail(SR_ERR_INVALID_ARGUMENT, at + "partition is -1, 0 or 1");
+        if (e.nontemporal < -1 || e.nontemporal > 1)
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "nontemporal is -1, 0 or 1");
+    }
+    auto before = [](const sr_tune_entry& a, const sr_tune_entry& b) {
+        if (a.dtype != b.dtype) return a.dtype < b.dtype;
+        if (a.pairs != b.pairs) return a.pairs < b.pairs;
+        return a.min_n < b.min_n;
+    };
+    std::sort(rows.begin(), rows.end(), before);
+    for (size_t i = 1; i < rows.size(); ++i)
+        if (!before(rows[i - 1], rows[i]))
+            return fail(SR_ERR_INVALID_ARGUMENT, "two tuning rows with the same dtype, pairs and min_n");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune.swap(rows);
+    return SR_OK;
+}
+
+sr_status sr_tune_get(sr_tune_entry* out, int64_t cap, int64_t* count) {
+    g_err.clear();
+    if (!count) return fail(SR_ERR_INVALID_ARGUMENT, "count is NULL");
+    if (cap < 0 || (cap > 0 && !out)) return fail(SR_ERR_INVALID_ARGUMENT, "bad output buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    *count = (int64_t)g_tune.size();
+    for (int64_t i = 0; i < cap && i < (int64_t)g_tune.size(); ++i) out[i] = g_tune[(size_t)i];
+    return SR_OK;
 }
 
 sr_status sr_profile_collect(const char* prefix, int64_t* launches, double* total_ms) {

@@ -17,6 +17,9 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsortrace.so")
+# Launch-shape table measured by the package's autotuner on gfx950; applied
+# when the library loads unless SR_TUNE_TABLE names another file or "none".
+TUNE_TABLE = os.path.join(_HERE, "tune_gfx950.json")
 
 SR_INT32, SR_UINT64, SR_FLOAT32 = 0, 1, 2
 DTYPES = {"int32": SR_INT32, "uint64": SR_UINT64, "float32": SR_FLOAT32}
@@ -29,7 +32,11 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
            "sr_release_stream", "sr_measure", "sr_workspace_bytes", "sr_last_stats", "sr_status_str",
            "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
            "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
-           "sr_server_records", "sr_server_destroy")
+           "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get")
+
+# Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
+TUNE_FIELDS = ("tile_variant", "merge_items", "partition", "nontemporal")
+TUNE_UNSET = {"tile_variant": -1, "merge_items": 0, "partition": -1, "nontemporal": -1}
 
 
 class SrStats(ctypes.Structure):
@@ -49,6 +56,12 @@ class SrRequestRecord(ctypes.Structure):
                 ("n", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class SrTuneEntry(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("pairs", ctypes.c_int32), ("min_n", ctypes.c_int64),
+                ("tile_variant", ctypes.c_int32), ("merge_items", ctypes.c_int32),
+                ("partition", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
 
 
 class SortraceError(RuntimeError):
@@ -94,11 +107,19 @@ def load(path: str = LIB_PATH):
     lib.sr_server_wait_idle.argtypes = [vp, ctypes.c_double]
     lib.sr_server_records.argtypes = [vp, ctypes.POINTER(SrRequestRecord), sz, ctypes.POINTER(sz)]
     lib.sr_server_destroy.argtypes = [vp]
+    lib.sr_tune_set.argtypes = [ctypes.POINTER(SrTuneEntry), i64]
+    lib.sr_tune_get.argtypes = [ctypes.POINTER(SrTuneEntry), i64, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
         if name not in ("sr_status_str", "sr_last_error_message"):
             getattr(lib, name).restype = i32
     lib.sr_server_now.restype = ctypes.c_double
     _lib = lib
+    table = os.environ.get("SR_TUNE_TABLE")
+    if table is None and os.path.exists(TUNE_TABLE):
+        table = TUNE_TABLE
+    if table and table != "none":
+        from . import autotune
+        autotune.apply(table)
     return lib
 
 
@@ -208,6 +229,33 @@ def workspace_bytes(dtype: str, with_payload: bool, n: int, nseg: int = 0) -> in
 def set_option(name: str, value: int) -> None:
     lib = load()
     _check(lib.sr_set_option(name.encode(), int(value)), "sr_set_option")
+
+
+def tune_set(rows) -> None:
+    """Replace the tuning table.  rows: dicts with dtype ("int32", "uint64",
+    "float32"), pairs (bool), min_n and any of TUNE_FIELDS (missing = unset)."""
+    lib = load()
+    buf = (SrTuneEntry * max(1, len(rows)))()
+    for i, r in enumerate(rows):
+        e = buf[i]
+        e.dtype = DTYPES[r["dtype"]]
+        e.pairs = int(bool(r.get("pairs", False)))
+        e.min_n = int(r.get("min_n", 0))
+        for f in TUNE_FIELDS:
+            setattr(e, f, int(r.get(f, TUNE_UNSET[f])))
+    _check(lib.sr_tune_set(buf, len(rows)), "sr_tune_set")
+
+
+def tune_get() -> list:
+    """The tuning table as a list of dicts (sorted by dtype, pairs, min_n)."""
+    lib = load()
+    cnt = ctypes.c_int64()
+    _check(lib.sr_tune_get(None, 0, ctypes.byref(cnt)), "sr_tune_get")
+    buf = (SrTuneEntry * max(1, cnt.value))()
+    _check(lib.sr_tune_get(buf, cnt.value, ctypes.byref(cnt)), "sr_tune_get")
+    names = {v: k for k, v in DTYPES.items()}
+    return [{"dtype": names[e.dtype], "pairs": bool(e.pairs), "min_n": e.min_n,
+             **{f: getattr(e, f) for f in TUNE_FIELDS}} for e in buf[:cnt.value]]
 
 
 def profile_collect(prefix: str = ""):

@@ -64,3 +64,88 @@ def test_host_side_validation(lib):
     b = ctypes.c_size_t()
     assert lib.sr_workspace_bytes(0, 0, 1000, 0, ctypes.byref(b)) == 0 and b.value >= 4000
     assert lib.sr_workspace_bytes(5, 0, 1000, 0, ctypes.byref(b)) == 1
+
+
+@pytest.fixture
+def keep_table(lib):
+    """Restore the table the library had loaded after the test."""
+    from paper_1609_04471_amd import sortrace
+    saved = sortrace.tune_get()
+    yield
+    sortrace.tune_set(saved)
+
+
+def test_tuning_table_validation(lib, keep_table):
+    from paper_1609_04471_amd import sortrace
+    sortrace.tune_set([])
+    assert sortrace.tune_get() == []
+    rows = [{"dtype": "uint64", "pairs": True, "min_n": 1 << 20, "partition": 1, "nontemporal": 0},
+            {"dtype": "int32", "pairs": False, "min_n": 1 << 22, "tile_variant": 0, "partition": 1},
+            {"dtype": "int32", "pairs": False, "min_n": 0, "tile_variant": 1, "merge_items": 16}]
+    sortrace.tune_set(rows)
+    got = sortrace.tune_get()
+    assert [(r["dtype"], r["pairs"], r["min_n"]) for r in got] == \
+        [("int32", False, 0), ("int32", False, 1 << 22), ("uint64", True, 1 << 20)]
+    assert got[0]["merge_items"] == 16 and got[0]["partition"] == -1 and got[0]["nontemporal"] == -1
+    assert got[2]["tile_variant"] == -1 and got[2]["merge_items"] == 0
+    bad = [
+        {"dtype": "int32", "min_n": -1},
+        {"dtype": "int32", "min_n": 0, "tile_variant": 2},
+        {"dtype": "int32", "min_n": 0, "merge_items": 12},
+        {"dtype": "int32", "min_n": 0, "partition": 3},
+        {"dtype": "int32", "min_n": 0, "nontemporal": -2},
+    ]
+    for r in bad:
+        with pytest.raises(sortrace.SortraceError) as ei:
+            sortrace.tune_set([rows[0], r])
+        assert ei.value.status == 1, r
+        assert sortrace.tune_get() == got      # unchanged
+    with pytest.raises(sortrace.SortraceError):
+        sortrace.tune_set([rows[2], dict(rows[2], merge_items=8)])  # same (dtype, pairs, min_n)
+    e = (sortrace.SrTuneEntry * 1)()
+    e[0].dtype = 9
+    assert lib.sr_tune_set(e, 1) == 1 and b"dtype" in lib.sr_last_error_message()
+    assert lib.sr_tune_set(None, 3) == 1
+    assert lib.sr_tune_set(e, 1025) == 1
+    cnt = ctypes.c_int64()
+    assert lib.sr_tune_get(None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 3
+    assert lib.sr_tune_get(None, 0, None) == 1
+    sortrace.tune_set([])
+    assert sortrace.tune_get() == []
+    assert lib.sr_set_option(b"merge_nontemporal", 2) == 1
+    assert lib.sr_set_option(b"merge_nontemporal", -1) == 0
+    assert lib.sr_set_option(b"merge_items", 12) == 1
+    assert lib.sr_set_option(b"merge_items", 0) == 0
+    assert lib.sr_set_option(b"partition_min_n", -2) == 1
+    assert lib.sr_set_option(b"partition_min_n", -1) == 0
+
+
+def test_autotune_host_logic(tmp_path, keep_table):
+    import json
+    from paper_1609_04471_amd import autotune, sortrace
+    c = autotune.candidates("int32", False)
+    # 2 tiles x (fused: 2 merge widths + persistent: 2 store kinds)
+    assert len(c) == 8 and len({json.dumps(x, sort_keys=True) for x in c}) == 8
+    assert all(set(x) <= set(sortrace.TUNE_FIELDS) for x in c)
+    for dt, pairs in (("uint64", False), ("int32", True), ("float32", True), ("uint64", True)):
+        c = autotune.candidates(dt, pairs)
+        assert c == [{"partition": 0}, {"partition": 1, "nontemporal": 0}, {"partition": 1, "nontemporal": 1}]
+    sizes = autotune.band_sizes("int32", False, 16, 20, 2)
+    assert sizes == [1 << 16, 1 << 18, 1 << 20]
+    assert autotune.band_starts(sizes) == [0, 1 << 17, 1 << 19]
+    rows = [{"dtype": "int32", "pairs": False, "min_n": 0, "partition": 0, "merge_items": 8},
+            {"dtype": "int32", "pairs": False, "min_n": 9, "partition": 0, "merge_items": 8},
+            {"dtype": "int32", "pairs": False, "min_n": 99, "partition": 1, "nontemporal": 0},
+            {"dtype": "int32", "pairs": True, "min_n": 0, "partition": 1, "nontemporal": 0}]
+    assert [r["min_n"] for r in autotune.compress(rows)] == [0, 99, 0]
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"format": autotune.FORMAT, "rows": rows}))
+    assert autotune.apply(str(p)) == autotune.validate(json.loads(p.read_text()))
+    assert len(sortrace.tune_get()) == 4
+    p.write_text(json.dumps({"format": "other", "rows": rows}))
+    with pytest.raises(ValueError):
+        autotune.apply(str(p))
+    # the shipped table names only swept shapes
+    for r in autotune.validate(json.load(open(sortrace.TUNE_TABLE))):
+        shape = {k: v for k, v in r.items() if k in sortrace.TUNE_FIELDS}
+        assert shape in autotune.candidates(r["dtype"], r["pairs"]), r

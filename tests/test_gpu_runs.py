@@ -171,11 +171,15 @@ def test_runs_switch_off(gpu):
 
 @pytest.mark.parametrize("name,k", [("even_teeth", 8), ("equal_teeth", 64), ("even_teeth", 3)])
 def test_runs_with_partition_launch(gpu, name, k):
-    """Above 2^22 keys the leaf merges take their co-ranks from the partition
-    launch and run persistent and double-buffered."""
+    """With the separate partition launch the leaf merges take their co-ranks
+    from it and run persistent and double-buffered."""
     n = 5_000_011
     a = inputs.class_int32(name, n, k, seed=k)
-    st = check(gpu, a)
+    gpu.set_option("partition_min_n", 0)
+    try:
+        st = check(gpu, a)
+    finally:
+        gpu.set_option("partition_min_n", -1)
     assert st["path"] == "runs" and st["merge_passes"] >= 2, st
 
 

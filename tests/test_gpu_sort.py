@@ -180,7 +180,7 @@ def test_separate_partition_launch(gpu, n):
         wk, wp = oracle.sort_pairs(k, p)
         assert np.array_equal(gk, wk) and np.array_equal(gp, wp)
     finally:
-        gpu.set_option("partition_min_n", 1 << 22)
+        gpu.set_option("partition_min_n", -1)
 
 
 def _near(n, seed, frac=100, ties=1):
@@ -277,4 +277,4 @@ def test_tuning_variants_same_bytes(gpu, tile_variant, merge_items):
             assert np.array_equal(bits(gpu_sort_keys(gpu, f, "float32")), bits(oracle.sort_keys(f)))
     finally:
         gpu.set_option("tile_variant", -1)
-        gpu.set_option("merge_items", 8)
+        gpu.set_option("merge_items", 0)
