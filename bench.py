@@ -473,7 +473,8 @@ def classes_section(args, torch, np, inputs, sortrace, dev, stream):
             src = torch.from_numpy(inputs.class_int32(name, n, k, inputs.seed_for(6, ci, k))).to(dev)
             ms, st = time_sort(src, work, 10)
             gms, _ = time_sort(src, work, 5, force=3)
-            rows.append((k, ms, gms, st["path"], st["passes"]))
+            m = sortrace.presortedness(src, inv=True)
+            rows.append((k, ms, gms, st["path"], st["passes"], (m["run"], m["mono"], m["inv"])))
         mean = statistics.mean(r[1] for r in rows)
         gmean = statistics.mean(r[2] for r in rows)
         paths = {}
@@ -481,8 +482,22 @@ def classes_section(args, torch, np, inputs, sortrace, dev, stream):
             paths[r[3]] = paths.get(r[3], 0) + 1
         out[name] = {"ms_mean_over_k": round(mean, 5), "Mkeys_s": round(n / (mean / 1e3) / 1e6, 1),
                      "general_ms_mean": round(gmean, 5), "speedup_vs_general": round(gmean / mean, 2),
-                     "paths": paths, "passes": {str(r[0]): r[4] for r in rows}}
+                     "paths": paths, "passes": {str(r[0]): r[4] for r in rows},
+                     "run_mono_inv": {str(r[0]): r[5] for r in rows}}
         log(f"classes 2M {name}: {out[name]}")
+    # device time of the Sec. 2 measures on one 2M input
+    src = torch.from_numpy(inputs.class_int32("exchange", n, 64, 1)).to(dev)
+    meas = {}
+    for label, inv in (("run_mono_ms", False), ("run_mono_inv_ms", True)):
+        times = []
+        for i in range(6):
+            t0 = time.perf_counter()
+            sortrace.presortedness(src, inv=inv)   # synchronizes
+            if i:
+                times.append((time.perf_counter() - t0) * 1e3)
+        meas[label] = round(statistics.median(times), 4)
+    log(f"measures at 2M (host-timed, include allocation and the copy back): {meas}")
+    out["measure_time_2M"] = meas
     del work
     big = {}
     if not args.no_big:

@@ -186,6 +186,35 @@ sr_status sr_server_destroy(sr_server *s);
  */
 sr_status sr_measure(sr_dtype dt, const void *keys, size_t n, int64_t *out_host, void *stream);
 
+/*
+ * The three presortedness measures of Sec. 2 on the device (keys are not
+ * modified; they are compared in the order the sort uses):
+ *   Run(A)  = |{i : a_i > a_{i+1}}| + 1;
+ *   Mono(A) = the least k such that A is a concatenation of k contiguous
+ *             pieces, each sorted or reversely sorted (nondecreasing or
+ *             nonincreasing; a piece of equal keys is both);
+ *   Inv(A)  = |{(i, j) : i < j, a_i > a_j}|, only when flags has
+ *             SR_MEASURE_INV (it costs a merge sort of a copy:
+ *             log2(n/16) + 1 launches over 2 x n x key-size bytes of scratch).
+ * For n = 0 every measure is 0; for n = 1, run = mono = 1.
+ * out_host is HOST memory; the call allocates its scratch with hipMalloc,
+ * frees it, and synchronizes `stream`.  Errors: bad arguments as for
+ * sr_sort_keys, an unknown flag, NULL out_host (SR_ERR_INVALID_ARGUMENT);
+ * no memory for the scratch (SR_ERR_OUT_OF_MEMORY).
+ */
+typedef struct {
+    int64_t descents;  /* |{i : a_i > a_{i+1}}| */
+    int64_t ascents;   /* |{i : a_i < a_{i+1}}| */
+    int64_t run;       /* Run(A) */
+    int64_t mono;      /* Mono(A) */
+    int64_t inv;       /* Inv(A); -1 when not asked for */
+} sr_presortedness;
+
+#define SR_MEASURE_INV 1
+
+sr_status sr_measure_presortedness(sr_dtype dt, const void *keys, size_t n, int32_t flags,
+                                   sr_presortedness *out_host, void *stream);
+
 /* Workspace bytes the library would hold for a call of this shape. */
 sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nseg, size_t *bytes);
 

@@ -2061,6 +2061,8 @@ __global__ __launch_bounds__(256) void k_copy16(uint4* dst, const uint4* src, in
 // ======================================================================
 // Host side
 // ======================================================================
+#include "sr_internal.hpp"
+
 namespace {
 
 using namespace sr;
@@ -2732,6 +2734,12 @@ sr_status check_keys(sr_dtype dt, const void* keys, size_t n) {
 }
 
 }  // namespace
+
+namespace sr {
+sr_status api_fail(sr_status s, const std::string& msg) { return fail(s, msg); }
+void api_clear_error() { g_err.clear(); }
+sr_status api_check_keys(sr_dtype dt, const void* keys, size_t n) { return check_keys(dt, keys, n); }
+}  // namespace sr
 
 // ======================================================================
 // C ABI

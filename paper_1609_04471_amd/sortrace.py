@@ -32,7 +32,9 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
            "sr_release_stream", "sr_measure", "sr_workspace_bytes", "sr_last_stats", "sr_status_str",
            "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
            "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
-           "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get")
+           "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get",
+           "sr_measure_presortedness")
+SR_MEASURE_INV = 1
 
 # Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
 TUNE_FIELDS = ("tile_variant", "merge_items", "partition", "nontemporal")
@@ -62,6 +64,11 @@ class SrTuneEntry(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("pairs", ctypes.c_int32), ("min_n", ctypes.c_int64),
                 ("tile_variant", ctypes.c_int32), ("merge_items", ctypes.c_int32),
                 ("partition", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+
+
+class SrPresortedness(ctypes.Structure):
+    _fields_ = [("descents", ctypes.c_int64), ("ascents", ctypes.c_int64), ("run", ctypes.c_int64),
+                ("mono", ctypes.c_int64), ("inv", ctypes.c_int64)]
 
 
 class SortraceError(RuntimeError):
@@ -107,6 +114,7 @@ def load(path: str = LIB_PATH):
     lib.sr_server_wait_idle.argtypes = [vp, ctypes.c_double]
     lib.sr_server_records.argtypes = [vp, ctypes.POINTER(SrRequestRecord), sz, ctypes.POINTER(sz)]
     lib.sr_server_destroy.argtypes = [vp]
+    lib.sr_measure_presortedness.argtypes = [i32, vp, sz, ctypes.c_int32, ctypes.POINTER(SrPresortedness), vp]
     lib.sr_tune_set.argtypes = [ctypes.POINTER(SrTuneEntry), i64]
     lib.sr_tune_get.argtypes = [ctypes.POINTER(SrTuneEntry), i64, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS:
@@ -206,6 +214,17 @@ def measure(keys, dtype: str | None = None, stream=None):
     _check(lib.sr_measure(_key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(), out,
                           _stream(stream)), "sr_measure")
     return int(out[0]), int(out[1])
+
+
+def presortedness(keys, dtype: str | None = None, inv: bool = False, stream=None) -> dict:
+    """Run, Mono (and Inv when asked) of keys, with descents and ascents.
+    inv is -1 unless asked for.  Synchronizes."""
+    lib = load()
+    out = SrPresortedness()
+    _check(lib.sr_measure_presortedness(_key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(),
+                                        SR_MEASURE_INV if inv else 0, ctypes.byref(out), _stream(stream)),
+           "sr_measure_presortedness")
+    return {f: int(getattr(out, f)) for f, _ in SrPresortedness._fields_}
 
 
 def last_stats(stream=None) -> dict:

@@ -64,6 +64,15 @@ def test_host_side_validation(lib):
     b = ctypes.c_size_t()
     assert lib.sr_workspace_bytes(0, 0, 1000, 0, ctypes.byref(b)) == 0 and b.value >= 4000
     assert lib.sr_workspace_bytes(5, 0, 1000, 0, ctypes.byref(b)) == 1
+    from paper_1609_04471_amd import sortrace
+    m = sortrace.SrPresortedness()
+    assert lib.sr_measure_presortedness(0, vp(0x1000), 10, 2, ctypes.byref(m), None) == 1  # unknown flag
+    assert lib.sr_measure_presortedness(0, vp(0x1000), 10, 0, None, None) == 1             # NULL output
+    assert lib.sr_measure_presortedness(0, vp(0x1002), 10, 0, ctypes.byref(m), None) == 1  # misaligned
+    assert lib.sr_measure_presortedness(0, None, 1, 1, ctypes.byref(m), None) == 0         # n <= 1
+    assert (m.run, m.mono, m.inv, m.descents) == (1, 1, 0, 0)
+    assert lib.sr_measure_presortedness(0, None, 0, 0, ctypes.byref(m), None) == 0
+    assert (m.run, m.mono, m.inv) == (0, 0, -1)
 
 
 @pytest.fixture
