@@ -3,8 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library never does, and the
 two share no code: the oracle is the plain C file ``sortrace_oracle.c``
-(stable top-down mergesort, insertion sort, brute-force selection, and the
-presortedness measures Run/Inv/Mono of Sec. 2 of the Sort Race paper), driven
+(stable top-down mergesort, insertion sort, brute-force selection, the list
+sort of the heavy items, and the presortedness measures Run/Inv/Mono of
+Sec. 2 of the Sort Race paper), driven
 here through ctypes on numpy arrays.
 
 Every function takes a numpy array and returns a NEW sorted array (the input
@@ -53,6 +54,8 @@ def _load():
             getattr(lib, name).restype = c_int
         lib.oracle_sort_segmented.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_size_t]
         lib.oracle_sort_segmented.restype = c_int
+        lib.oracle_sort_lists.argtypes = [c_void_p, c_size_t, c_size_t]
+        lib.oracle_sort_lists.restype = c_int
         for name in ("oracle_run", "oracle_ascents", "oracle_inv", "oracle_mono"):
             getattr(lib, name).argtypes = [c_int, c_void_p, c_size_t]
             getattr(lib, name).restype = ctypes.c_int64
@@ -100,6 +103,15 @@ def sort_segmented(keys: np.ndarray, offsets: np.ndarray, payload: np.ndarray | 
     _check(_load().oracle_sort_segmented(_dt(k), _ptr(k), _ptr(p), _ptr(off), off.size - 1),
            "sort_segmented")
     return k if p is None else (k, p)
+
+
+def sort_lists(lists: np.ndarray) -> np.ndarray:
+    """Stable mergesort of the rows of an (n, L) int32 array, compared word by
+    word from the first (the heavy list items of Sec. 2)."""
+    a = np.ascontiguousarray(lists, dtype=np.int32).copy()
+    assert a.ndim == 2 and a.shape[1] >= 1
+    _check(_load().oracle_sort_lists(_ptr(a), a.shape[0], a.shape[1]), "sort_lists")
+    return a
 
 
 def insertion_sort(keys: np.ndarray, payload: np.ndarray | None = None):

@@ -41,6 +41,9 @@
  *                                          strictly greater, hence stable
  *   oracle_brute_sort                      O(n^2) definition: repeatedly
  *                                          take the minimum (key, index)
+ *   oracle_sort_lists                      the heavy items of Sec. 2: lists
+ *                                          of int32 compared word by word
+ *                                          (lexicographic), same mergesort
  *   oracle_run / oracle_inv / oracle_mono  presortedness measures of Sec. 2
  *                                          (Run, Inv, Mono)
  *
@@ -335,6 +338,50 @@ int oracle_brute_sort(int dtype, void *keys, uint32_t *payload, size_t n)
 /* Run(A) of Sec. 2: the number of descents a_i > a_{i+1}, plus one.  An
  * empty array has no runs (reading: the +1 counts the first run, and there
  * is none). */
+/* ------------------------------------------------- lists (heavy items) */
+
+/* Sec. 2 lists its first classes with items that are lists of integers of
+ * 64, 256 or 1024 bytes.  The order taken for them: word by word from the
+ * first, each word a signed int32; the first unequal word decides (equal
+ * lists are equal).  The comparator needs the list length, which this
+ * single-threaded test oracle keeps in a file-scope variable for the
+ * duration of one call. */
+static size_t g_list_words;
+
+static int less_list(const unsigned char *a, const unsigned char *b)
+{
+    for (size_t w = 0; w < g_list_words; w++) {
+        int32_t x, y;
+        memcpy(&x, a + 4 * w, 4);
+        memcpy(&y, b + 4 * w, 4);
+        if (x != y)
+            return x < y;
+    }
+    return 0;
+}
+
+int oracle_sort_lists(int32_t *lists, size_t n, size_t words)
+{
+    if (words == 0)
+        return -1;
+    if (n == 0)
+        return 0;
+    if (lists == NULL)
+        return -1;
+    rec_t r;
+    r.ks = 4 * words;
+    r.rs = 4 * words;
+    r.with_payload = 0;
+    r.less = less_list;
+    g_list_words = words;
+    unsigned char *tmp = (unsigned char *)malloc(n * r.rs);
+    if (!tmp)
+        return -1;
+    msort(&r, (unsigned char *)lists, tmp, 0, n);
+    free(tmp);
+    return 0;
+}
+
 int64_t oracle_run(int dtype, const void *keys, size_t n)
 {
     less_fn less = less_for(dtype);

@@ -282,3 +282,67 @@ def test_pins_catch_planted_mistakes(tmp_path):
     assert ok, "the real oracle must pass its own pins"
     for name in MUTATIONS:
         assert not _pins_pass(_mutant_sorts(tmp_path, name)), f"mutation {name} not caught"
+
+
+# ------------------------------- P8 heavy list items (Sec. 2, lists of ints)
+
+def _lists_pins_pass(sort_lists):
+    """Rows of an (n, L) int32 array in word-by-word order: checked against
+    numpy's lexsort (last key primary, so the columns go in reversed) and,
+    for tiny cases, against Python's tuple order over every permutation."""
+    rng = np.random.default_rng(8)
+    for L in (1, 2, 3, 5, 16):
+        for n in (0, 1, 7, 300):
+            a = rng.integers(-2, 2, size=(n, L)).astype(np.int32)
+            a[::5, 0] = np.iinfo(np.int32).min
+            a[1::7, -1] = np.iinfo(np.int32).max
+            want = a[np.lexsort(a.T[::-1])] if n else a
+            if not np.array_equal(sort_lists(a), want):
+                return False
+    rows = [(0, 1, -1), (0, 1, 2), (-5, 9, 9), (0, 0, 7), (0, 1, -1), (3, -8, 0)]
+    for perm in itertools.permutations(range(len(rows))):
+        a = np.array([rows[i] for i in perm], dtype=np.int32)
+        if [tuple(r) for r in sort_lists(a)] != sorted(rows):
+            return False
+    return True
+
+
+LIST_MUTATIONS = {
+    "first_word_only": ("        if (x != y)\n            return x < y;\n    }\n    return 0;",
+                        "        if (x != y)\n            return x < y;\n        break;\n    }\n    return 0;"),
+    "words_unsigned": ("        int32_t x, y;\n        memcpy(&x, a + 4 * w, 4);",
+                       "        uint32_t x, y;\n        memcpy(&x, a + 4 * w, 4);"),
+    "last_word_first": ("        memcpy(&x, a + 4 * w, 4);\n        memcpy(&y, b + 4 * w, 4);",
+                        "        memcpy(&x, a + 4 * (g_list_words - 1 - w), 4);\n"
+                        "        memcpy(&y, b + 4 * (g_list_words - 1 - w), 4);"),
+}
+
+
+def _mutant_lists(tmp_path, name):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "sortrace_oracle.c")).read()
+    old, new = LIST_MUTATIONS[name]
+    assert old in src, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", str(path), "-o", str(so)])
+    lib = ctypes.CDLL(str(so))
+    lib.oracle_sort_lists.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_size_t]
+
+    def sort_lists(a):
+        a = np.ascontiguousarray(a, dtype=np.int32).copy()
+        lib.oracle_sort_lists(a.ctypes.data, a.shape[0], a.shape[1])
+        return a
+    return sort_lists
+
+
+def test_list_sort_pins():
+    assert _lists_pins_pass(oracle.sort_lists)
+    a = np.arange(-50, 50, dtype=np.int32)[::-1].reshape(-1, 1)
+    assert np.array_equal(oracle.sort_lists(a)[:, 0], np.sort(a[:, 0]))  # L = 1: plain int32 order
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc needed")
+def test_list_pins_catch_planted_mistakes(tmp_path):
+    for name in LIST_MUTATIONS:
+        assert not _lists_pins_pass(_mutant_lists(tmp_path, name)), f"mutation {name} not caught"
