@@ -83,9 +83,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-classes", action="store_true", help="skip the Sec. 2 presorted-class section")
     ap.add_argument("--no-configs", action="store_true", help="skip the 2^20 keys and 2^24 pairs section")
+    ap.add_argument("--no-lists", action="store_true", help="skip the heavy list items section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve",
-                                       "classes", "configs"],
+                                       "classes", "configs", "lists"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -267,6 +268,12 @@ def main():
         cfgs = configs_section(torch, np, inputs, sortrace, dev, stream)
     result["configs"] = cfgs
 
+    # ------------------------------------------------------------ heavy list items
+    lists = None
+    if not args.no_lists and args.only in (None, "lists"):
+        lists = lists_section(torch, inputs, sortrace, dev)
+    result["lists"] = lists
+
     # ------------------------------------------------------------ Sec. 2 classes
     classes = None
     if not args.no_classes and args.only in (None, "classes"):
@@ -376,11 +383,42 @@ def main():
         "segmented_4096": result.get("segmented"),
         "presorted_classes": result.get("classes"),
         "keys_2p20_and_pairs_2p24": result.get("configs"),
+        "heavy_lists": result.get("lists"),
         "serving": result.get("serving"),
         "tuning": result.get("tuning"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def lists_section(torch, inputs, sortrace, dev):
+    """Heavy items of Sec. 2: random lists of 16, 64 and 256 int32 (64, 256
+    and 1024 bytes), n = 200,000 (the size of Tables 2-3) and 2,000,000.
+    sr_sort_lists synchronizes, so the host clock times each call; the input
+    is restored (untimed) before every call.  Bytes: the prefix-key pairs
+    sort plus one read and one gather write of the lists."""
+    out = {}
+    for n in (200_000, 2_000_000):
+        for L in (16, 64, 256):
+            src = torch.from_numpy(inputs.random_lists(n, L, seed=n + L)).to(dev)
+            work = torch.empty_like(src)
+            times = []
+            for i in range(6):
+                work.copy_(src)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sortrace.sort_lists(work)
+                if i:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            ok = bool(((work[1:, 0] > work[:-1, 0]) | (work[1:, 0] == work[:-1, 0])).all())
+            ms = statistics.median(times)
+            key = f"n{n}_words{L}"
+            out[key] = {"ms_median": round(ms, 4), "Mlists_s": round(n / (ms / 1e3) / 1e6, 2),
+                        "list_GBps": round(2 * n * L * 4 / (ms / 1e3) / 1e9, 1), "first_word_sorted": ok}
+            log(f"lists {key}: {out[key]}")
+            del src, work
+    torch.cuda.synchronize()
+    return out
 
 
 def configs_section(torch, np, inputs, sortrace, dev, stream):

@@ -113,6 +113,22 @@ sr_status sr_sort_segmented(sr_dtype dt, void *keys, uint32_t *payload, size_t n
                             const int64_t *offsets, size_t nseg, void *stream);
 
 /*
+ * Heavy items (Sec. 2: random lists of 16, 64 or 256 integers): n lists of
+ * `words` int32 each, row-major at device pointer `lists` (list i at
+ * lists + i * words), sorted in place into word-by-word order from the first
+ * word (each word a signed int32; the first unequal word decides), stable
+ * (equal lists keep their input order).  The lists are ordered through
+ * 64-bit prefix keys of two words with the list index as payload (a stable
+ * pairs sort), ties refined two words at a time by segmented sorts of the
+ * tied positions, then gathered once.  The call allocates its scratch with
+ * hipMalloc (about 40 bytes per list plus one copy of the lists), reads the
+ * tie count back after each refinement round, and synchronizes `stream`.
+ * Errors: words outside 1 .. 2^20, n above 2^32 - 1, NULL or misaligned
+ * lists (SR_ERR_INVALID_ARGUMENT); no memory (SR_ERR_OUT_OF_MEMORY).
+ */
+sr_status sr_sort_lists(int32_t *lists, size_t n, int32_t words, void *stream);
+
+/*
  * Batched sort of nseg independent arrays, each in its own device buffer:
  * array s starts at keys_ptrs[s] and has lens[s] keys of type dt.  keys_ptrs
  * and lens are DEVICE arrays (8-byte aligned) of nseg entries; total is the

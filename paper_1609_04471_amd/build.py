@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libsortrace.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["sr_engine.hip", "sr_server.hip", "sr_measure.hip"]
+SOURCES = ["sr_engine.hip", "sr_server.hip", "sr_measure.hip", "sr_records.hip"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

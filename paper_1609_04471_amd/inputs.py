@@ -352,6 +352,16 @@ def segments_int32(nseg: int, seed: int, lo: int = 16, hi: int = 262144):
 
 # ----------------------------------------------------------- float32 mix
 
+def random_lists(n: int, words: int, seed: int, lo: int | None = None, hi: int | None = None) -> np.ndarray:
+    """(n, words) int32 lists (the heavy items of Sec. 2): uniform over all
+    int32 values, or over [lo, hi) when given (small ranges make prefixes
+    tie)."""
+    u = stream(seed, n * words)
+    if lo is None:
+        return (u & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32).reshape(n, words)
+    return (lo + (u % np.uint64(hi - lo)).astype(np.int64)).astype(np.int32).reshape(n, words)
+
+
 def normal_float32(n: int, seed: int, specials: bool = True) -> np.ndarray:
     """N(0,1) float32; with ``specials``: 1% repeats, then 0.1% each of +0,
     -0, +qNaN, -qNaN and NaNs with random sign and payload."""

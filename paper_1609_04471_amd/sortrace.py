@@ -33,7 +33,7 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
            "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
            "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
            "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get",
-           "sr_measure_presortedness")
+           "sr_measure_presortedness", "sr_sort_lists")
 SR_MEASURE_INV = 1
 
 # Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     lib.sr_server_wait_idle.argtypes = [vp, ctypes.c_double]
     lib.sr_server_records.argtypes = [vp, ctypes.POINTER(SrRequestRecord), sz, ctypes.POINTER(sz)]
     lib.sr_server_destroy.argtypes = [vp]
+    lib.sr_sort_lists.argtypes = [vp, sz, ctypes.c_int32, vp]
     lib.sr_measure_presortedness.argtypes = [i32, vp, sz, ctypes.c_int32, ctypes.POINTER(SrPresortedness), vp]
     lib.sr_tune_set.argtypes = [ctypes.POINTER(SrTuneEntry), i64]
     lib.sr_tune_get.argtypes = [ctypes.POINTER(SrTuneEntry), i64, ctypes.POINTER(ctypes.c_int64)]
@@ -216,6 +217,18 @@ def measure(keys, dtype: str | None = None, stream=None):
     return int(out[0]), int(out[1])
 
 
+def sort_lists(lists, stream=None):
+    """Sort the rows of a 2-D int32 GPU tensor (n lists of `words` ints) in
+    place, word by word from the first, stable.  Synchronizes."""
+    import torch
+    if lists.dim() != 2 or lists.dtype != torch.int32:
+        raise ValueError("lists must be a 2-D int32 tensor")
+    lib = load()
+    _check(lib.sr_sort_lists(_dev(lists, "lists"), lists.shape[0], lists.shape[1], _stream(stream)),
+           "sr_sort_lists")
+    return lists
+
+
 def presortedness(keys, dtype: str | None = None, inv: bool = False, stream=None) -> dict:
     """Run, Mono (and Inv when asked) of keys, with descents and ascents.
     inv is -1 unless asked for.  Synchronizes."""
@@ -223,7 +236,7 @@ def presortedness(keys, dtype: str | None = None, inv: bool = False, stream=None
     out = SrPresortedness()
     _check(lib.sr_measure_presortedness(_key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(),
                                         SR_MEASURE_INV if inv else 0, ctypes.byref(out), _stream(stream)),
-           "sr_measure_presortedness")
+           "sr_measure_presortedness", "sr_sort_lists")
     return {f: int(getattr(out, f)) for f, _ in SrPresortedness._fields_}
 
 
