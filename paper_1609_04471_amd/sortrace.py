@@ -236,7 +236,7 @@ def presortedness(keys, dtype: str | None = None, inv: bool = False, stream=None
     out = SrPresortedness()
     _check(lib.sr_measure_presortedness(_key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(),
                                         SR_MEASURE_INV if inv else 0, ctypes.byref(out), _stream(stream)),
-           "sr_measure_presortedness", "sr_sort_lists")
+           "sr_measure_presortedness")
     return {f: int(getattr(out, f)) for f, _ in SrPresortedness._fields_}
 
 
