@@ -1957,15 +1957,49 @@ __global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S
                                                  const int* seg_passes, const SegCtl* sc,
                                                  typename C::S* const* ptrs) {
     using TS = TileSort<C, WG, IT, PAIRS>;
+    constexpr int NW = WG / kWave;
     __shared__ typename TS::Smem sm;
+    __shared__ int s_small[NW];
     const int64_t total = sc->total_tiles;
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * per;
     const int64_t b1 = (b0 + per) < total ? (b0 + per) : total;
     if (b0 >= b1) return;
     int64_t s = find_seg(tile_pre, nseg, b0);
-    for (int64_t b = b0; b < b1; ++b) {
+    const int wave = threadIdx.x / kWave;
+    for (int64_t b = b0; b < b1;) {
         while (tile_pre[s + 1] <= b) ++s;
+        if (off[s + 1] - off[s] <= TS::WAVE_T) {
+            // Segments of at most 64 * IT keys (one tile each): this one and
+            // up to NW - 1 more in a row are sorted at once, one per wavefront.
+            const int64_t bw = b + wave;
+            int64_t sw = s;
+            int small = 0;
+            if (bw < b1) {
+                while (tile_pre[sw + 1] <= bw) ++sw;
+                small = (off[sw + 1] - off[sw]) <= TS::WAVE_T ? 1 : 0;
+            }
+            if (__lane_id() == 0) s_small[wave] = small;
+            __syncthreads();
+            int run = 0;
+            while (run < NW && s_small[run]) ++run;  // >= 1: tile b is small
+            __syncthreads();
+            if (wave < run) {
+                const int64_t so = off[sw];
+                const int len = (int)(off[sw + 1] - so);
+                const bool to_s1 = (seg_passes[sw] & 1) != 0;
+                if (ptrs != nullptr) {
+                    typename C::S* us = ptrs[sw];
+                    TS::run_wave(us, to_s1 ? S1 + so : us, nullptr, nullptr, len);
+                } else {
+                    typename C::S* dst = to_s1 ? S1 : U;
+                    uint32_t* pdst = to_s1 ? PS1 : PU;
+                    TS::run_wave(U + so, dst + so, PAIRS ? PU + so : nullptr, PAIRS ? pdst + so : nullptr, len);
+                }
+            }
+            b += run;
+            continue;
+        }
         const int64_t so = off[s], len = off[s + 1] - so;
         const int64_t u = b - tile_pre[s];
         const int64_t base = so + u * TS::T;
@@ -1980,6 +2014,7 @@ __global__ __launch_bounds__(WG) void k_seg_tile(typename C::S* U, typename C::S
             TS::run(sm, U + base, dst + base, PAIRS ? PU + base : nullptr, PAIRS ? pdst + base : nullptr, valid);
         }
         __syncthreads();
+        ++b;
     }
 }
 

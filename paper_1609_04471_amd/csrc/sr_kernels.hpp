@@ -131,6 +131,38 @@ struct TileSort {
         }
     }
 
+    // A segment of at most 64 * IT keys sorted by the calling wavefront alone
+    // (registers and cross-lane exchanges, no LDS and no barrier); src may
+    // equal dst, psrc may equal pdst.
+    static constexpr int WAVE_T = kWave * IT;
+    static __device__ void run_wave(const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid) {
+        const int lane = (int)__lane_id();
+        E v[IT];
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int e = lane + r * kWave;
+            v[r] = make(e < valid ? C::enc(src[e]) : key_max<U>(), (uint32_t)e);
+        }
+        wave_sort(v);
+        // value r of lane L is output L * IT + r
+        uint32_t pv[PAIRS ? IT : 1];
+        if constexpr (PAIRS) {
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const int o = lane * IT + r;
+                pv[r] = o < valid ? psrc[v[r].p] : 0u;  // every read before any write
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int o = lane * IT + r;
+            if (o < valid) {
+                dst[o] = C::dec(key_of(v[r]));
+                if constexpr (PAIRS) pdst[o] = pv[r];
+            }
+        }
+    }
+
     static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid) {
         const int tid = threadIdx.x;
         E v[IT];

@@ -114,3 +114,41 @@ def test_graph_replays_match_eager(gpu):
             assert np.array_equal(plain.cpu().numpy(), oracle.sort_keys(a)), (rep, kind)
     finally:
         gpu.set_option("graph", 0)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint64", "float32"])
+def test_small_segments_one_per_wavefront(gpu, dtype):
+    """Segments of at most 64 x 16 keys are sorted by one wavefront each
+    (eight at a time per workgroup); runs of them mixed with empty and
+    tile-sized segments, on both sides of the 1024 / 512-key limits."""
+    rng = np.random.default_rng(17)
+    lengths = list(rng.integers(0, 1100, size=700)) + [1024, 1025, 512, 513, 64, 65, 1, 0, 0, 2]
+    lengths += [9000] + list(rng.integers(1, 40, size=300)) + [0] * 5 + [20_000, 1023]
+    off = offsets_of(lengths)
+    n = int(off[-1])
+    if dtype == "float32":
+        keys = inputs.normal_float32(n, seed=8)
+    elif dtype == "uint64":
+        keys = inputs.stream(8, n) >> np.uint64(50)        # many ties
+    else:
+        keys = (inputs.random_int32(n, seed=8) % 100).astype(np.int32)
+    got = run_keys(gpu, keys, off, dtype)
+    want = oracle.sort_segmented(keys, off)
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    if dtype != "float32":
+        pay = np.arange(n, dtype=np.uint32)[::-1].copy()
+        tk, tp = to_dev(keys), to_dev(pay.view(np.int32))
+        gpu.sort_segmented(tk, torch.from_numpy(off).to(DEV), payload=tp, dtype=dtype)
+        wk, wp = oracle.sort_segmented(keys, off, payload=pay)
+        assert np.array_equal(tk.cpu().numpy().view(keys.dtype), wk)
+        assert np.array_equal(tp.cpu().numpy().view(np.uint32), wp)
+
+
+def test_small_arrays_in_a_batch(gpu):
+    rng = np.random.default_rng(21)
+    arrays = [inputs.random_int32(int(m), seed=int(i)) for i, m in enumerate(rng.integers(1, 1200, size=200))]
+    arrays += [inputs.random_int32(30_000, seed=999)]
+    ts = [torch.from_numpy(a.copy()).to(DEV) for a in arrays]
+    gpu.sort_batch(ts, dtype="int32")
+    for a, t in zip(arrays, ts):
+        assert np.array_equal(t.cpu().numpy(), oracle.sort_keys(a))
