@@ -1120,7 +1120,6 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     const bool do_runs = runs_ok && (path == SR_PATH_RUNS || (path == SR_PATH_OUTLIER && ctl->dual));
     if (path != SR_PATH_OUTLIER && !do_runs) return;
     __shared__ U sk[kClsW];
-    __shared__ uint8_t kp[kClsW];                     // kept flags after the rounds
     __shared__ unsigned int kw[kClsWG], rw[kClsWG];   // per-thread kept masks, removals by others
     __shared__ int wtot[kClsWG / kWave];
     __shared__ int s_flag[2];
@@ -1149,7 +1148,6 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
         for (int r = 0; r < kClsPer; ++r) {
             const int j = tid + r * kClsWG;
             if (j < wn) sk[j] = C::enc(xv[r]);
-            kp[j] = j < wn ? 1 : 0;
         }
     }
     __syncthreads();
@@ -1161,10 +1159,12 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     // In a round every kept key q is compared with the next kept key j; at a
     // descent the larger key goes if dropping it restores the order with the
     // previous kept key, else the smaller if that restores it with the kept
-    // key after j, else both.  Neighbours come from register sweeps over the
-    // thread's own positions and, across its ends, from the kept masks the
-    // threads publish in LDS (kw); a removal of a position another thread
-    // owns goes to that thread's word rw by an LDS atomic OR.  All decisions
+    // key after j, else both.  A register sweep over the thread's own
+    // positions finds its descents; only at those (few, on nearly sorted
+    // input) are the neighbours looked up, by position, in the keys in LDS,
+    // across the thread's ends through the kept masks the threads publish in
+    // LDS (kw); a removal of a position another thread owns goes to that
+    // thread's word rw by an LDS atomic OR.  All decisions
     // of a round use the masks of the previous round, so the result does not
     // depend on thread timing.  A round without removals means the kept keys
     // are sorted.
@@ -1197,47 +1197,45 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
             const unsigned int w = kw[u];
             if (w != 0u) l1 = u * kClsPer + 31 - __builtin_clz(w);
         }
-        // backward sweep: the next two kept keys after each own position
-        U n1k[kClsPer], n2k[kClsPer];
+        // backward sweep: the descents, kept positions r whose next kept key
+        // is smaller (the rare case; everything else of a round is skipped
+        // for positions without one)
+        unsigned int desc = 0u;
         {
-            U k1 = r1 >= 0 ? sk[r1] : (U)0, k2 = r2 >= 0 ? sk[r2] : (U)0;
+            bool h = r1 >= 0;
+            U k1 = h ? sk[r1] : (U)0;
 #pragma unroll
             for (int r = kClsPer - 1; r >= 0; --r) {
-                n1k[r] = k1;
-                n2k[r] = k2;
                 if ((km >> r) & 1u) {
-                    k2 = k1;
+                    desc |= (h && key[r] > k1 ? 1u : 0u) << r;
                     k1 = key[r];
+                    h = true;
                 }
             }
         }
-        // forward sweep with the previous kept key: the removals
+        // the removals at each descent, from the previous kept key and the
+        // next two kept keys (read from LDS by position)
         unsigned int own_rem = 0u;
-        bool rem = false;
-        {
-            bool hp = l1 >= 0;
-            U pk = hp ? sk[l1] : (U)0;
-#pragma unroll
-            for (int r = 0; r < kClsPer; ++r) {
-                if ((km >> r) & 1u) {
-                    const unsigned int above = r + 1 < kClsPer ? km >> (r + 1) : 0u;
-                    const int na = __builtin_popcount(above);
-                    const bool h1 = na >= 1 || r1 >= 0;
-                    const bool h2 = na >= 2 || (na == 1 && r1 >= 0) || r2 >= 0;
-                    if (h1 && key[r] > n1k[r]) {
-                        bool ra = !hp || pk <= n1k[r];
-                        bool rb = !ra && (!h2 || key[r] <= n2k[r]);
-                        if (!ra && !rb) ra = rb = true;
-                        if (ra) own_rem |= 1u << r;
-                        if (rb) {
-                            if (na >= 1) own_rem |= 1u << (r + 1 + __builtin_ctz(above));
-                            else atomicOr(&rw[r1 / kClsPer], 1u << (r1 % kClsPer));
-                        }
-                        rem = true;
-                    }
-                    pk = key[r];
-                    hp = true;
-                }
+        const bool rem = desc != 0u;
+        while (desc != 0u) {
+            const int r = __builtin_ctz(desc);
+            desc &= desc - 1u;
+            const unsigned int above = r + 1 < kClsPer ? km >> (r + 1) : 0u;
+            const unsigned int below = km & ((1u << r) - 1u);
+            const int na = __builtin_popcount(above);
+            const int q1 = na >= 1 ? bj + r + 1 + __builtin_ctz(above) : r1;
+            const int q2 = na >= 2 ? bj + r + 1 + __builtin_ctz(above & (above - 1u)) : (na == 1 ? r1 : r2);
+            const U kr = sk[bj + r], n1 = sk[q1];
+            const bool h2 = q2 >= 0;
+            const bool hp = below != 0u || l1 >= 0;
+            const U pk = below != 0u ? sk[bj + 31 - __builtin_clz(below)] : (l1 >= 0 ? sk[l1] : (U)0);
+            bool ra = !hp || pk <= n1;
+            bool rb = !ra && (!h2 || kr <= sk[q2]);
+            if (!ra && !rb) ra = rb = true;
+            if (ra) own_rem |= 1u << r;
+            if (rb) {
+                if (na >= 1) own_rem |= 1u << (q1 - bj);
+                else atomicOr(&rw[r1 / kClsPer], 1u << (r1 % kClsPer));
             }
         }
         if (rem) s_flag[iter & 1] = 1;
@@ -1251,29 +1249,32 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
             break;
         }
     }
-    // the kept flags as bytes for the core pass below
-#pragma unroll
-    for (int r = 0; r < kClsPer; ++r) kp[bj + r] = (unsigned char)((km >> r) & 1u);
+    // the final kept masks, for the core pass below
+    kw[tid] = km;
     __syncthreads();
 
-    // the tile's core [c0, c1): kept ranks, first and last kept key
+    // the tile's core [c0, c1): this thread's 16 core positions as a bit
+    // mask cut out of the owners' kept masks, kept ranks, first and last
+    // kept key
     const int cs = (int)(c0 - w0), ce = (int)(c1 - w0);
     constexpr int CP = kClsTC / kClsWG;
-    int kpre[CP];
-    int kl = 0;
-#pragma unroll
-    for (int r = 0; r < CP; ++r) {
-        const int j = cs + tid * CP + r;
-        kpre[r] = kl;
-        kl += (j < ce && kp[j]) ? 1 : 0;
+    static_assert(CP == 16 && kClsPer >= CP, "a core stretch spans at most two owners' masks");
+    unsigned int bits;
+    {
+        const int p0 = cs + tid * CP;
+        const int u = p0 / kClsPer, o = p0 - u * kClsPer;
+        unsigned int m = kw[u] >> o;
+        if (u + 1 < kClsWG) m |= kw[u + 1] << (kClsPer - o);
+        const int nv = ce - p0;  // core positions of this thread
+        bits = nv <= 0 ? 0u : (m & (nv >= CP ? 0xFFFFu : ((1u << nv) - 1u)));
     }
+    const int kl = __builtin_popcount(bits);
     int x = kl;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
         const int y = __shfl_up(x, d);
         if (lane >= d) x += y;
     }
-    __syncthreads();
     if (lane == kWave - 1) wtot[wave] = x;
     __syncthreads();
     int koff = x - kl, kc = 0;
@@ -1283,27 +1284,15 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
         if (w < wave) koff += wtot[w];
     }
     if (kl > 0) {
-#pragma unroll
-        for (int r = 0; r < CP; ++r) {
-            const int j = cs + tid * CP + r;
-            if (j < ce && kp[j]) {
-                if (koff + kpre[r] == 0) s_first = sk[j];
-                if (koff + kpre[r] == kc - 1) s_last = sk[j];
-            }
-        }
+        const int p0 = cs + tid * CP;
+        if (koff == 0) s_first = sk[p0 + __builtin_ctz(bits)];
+        if (koff + kl == kc) s_last = sk[p0 + 31 - __builtin_clz(bits)];
     }
     __syncthreads();
 
     // publish: kept flags of the core as a bit mask (bit i of word w = core key
     // 32w + i), the kept count and the first/last kept key of the tile
     {
-        const int li0 = tid * CP;  // this thread's 16 core keys: one half of a 32-bit word
-        unsigned int bits = 0;
-#pragma unroll
-        for (int r = 0; r < CP; ++r) {
-            const int j = cs + li0 + r;
-            if (j < ce && kp[j]) bits |= 1u << r;
-        }
         const unsigned int other = (unsigned int)__shfl_xor((int)bits, 1);
         if ((tid & 1) == 0) flags[t * (kClsTC / 32) + tid / 2] = bits | (other << CP);
     }
