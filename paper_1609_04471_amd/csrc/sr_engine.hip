@@ -78,6 +78,17 @@ __device__ __forceinline__ int ceil_log2_dev(int64_t x) {
 }
 
 constexpr int kVerWG = 1024;
+constexpr int kVerQ = 8;  // consecutive tiles per verify thread per round
+constexpr int64_t kVerRound = (int64_t)kVerWG * kVerQ;
+
+// Slot of tile t's summary words (kept count, first and last kept key).
+// k_verify reads them in rounds of kVerRound tiles, thread i taking kVerQ
+// consecutive tiles; keeping tile r0 + i * kVerQ + q at r0 + q * kVerWG + i
+// makes each of those loads one coalesced row.  The arrays hold whole rounds.
+__device__ __forceinline__ int64_t ver_slot(int64_t t) {
+    const int64_t r0 = t / kVerRound * kVerRound, o = t - r0;
+    return r0 + (o % kVerQ) * kVerWG + o / kVerQ;
+}
 
 // ------------------------------------------------------------ natural runs
 // RUNS job: the natural runs of natural mergesort (Sec. 3) found in parallel,
@@ -1298,9 +1309,10 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     }
     if (tid == 0) {
         if (!converged) atomicOr(&ctl->bad_join, 1u);
-        tcount[t] = (unsigned long long)kc;
-        tfirst[t] = kc > 0 ? (unsigned long long)s_first : 0ull;
-        tlast[t] = kc > 0 ? (unsigned long long)s_last : 0ull;
+        const int64_t vs = ver_slot(t);
+        tcount[vs] = (unsigned long long)kc;
+        tfirst[vs] = kc > 0 ? (unsigned long long)s_first : 0ull;
+        tlast[vs] = kc > 0 ? (unsigned long long)s_last : 0ull;
     }
 }
 
@@ -1410,13 +1422,14 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
 __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
                                 const unsigned long long* tlast, const unsigned long long* tcount,
                                 unsigned long long* kpref_t, int64_t T_sort, double* ocost) {
-    // Rounds of kVerWG x 4 consecutive tiles (each thread four consecutive
-    // ones, so the loads of a wavefront share cache lines): the kept prefix
+    // Rounds of kVerWG x kVerQ consecutive tiles (each thread kVerQ
+    // consecutive ones, read from the ver_slot layout so that every load of a
+    // wavefront is one coalesced row): the kept prefix
     // continues a running base, and each tile's first kept key is checked
     // against the last kept key of the nearest earlier tile that kept any
     // (in this thread, in an earlier thread of the round -- a max-scan of
     // thread indices -- or in an earlier round).
-    constexpr int Q = 4;
+    constexpr int Q = kVerQ;
     __shared__ long long s_w[kVerWG / kWave];
     __shared__ unsigned long long s_lastk[kVerWG];
     __shared__ unsigned long long s_base, s_carry_key;
@@ -1437,9 +1450,10 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const bool ok = tb + q < ntiles;
-            cv[q] = ok ? tcount[tb + q] : 0ull;
-            fv[q] = ok ? tfirst[tb + q] : 0ull;
-            lv[q] = ok ? tlast[tb + q] : 0ull;
+            const int64_t vs = r0 + (int64_t)q * kVerWG + tid;  // ver_slot(tb + q)
+            cv[q] = ok ? tcount[vs] : 0ull;
+            fv[q] = ok ? tfirst[vs] : 0ull;
+            lv[q] = ok ? tlast[vs] : 0ull;
         }
         unsigned long long kept = 0, last = 0, first = 0;
         bool has = false, bad = false;
@@ -2419,7 +2433,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     // co-ranks of a merge pass; a RUNS pass has up to one extra chunk per leaf group
     const size_t co_bytes = round_up((size_t)(nchunks + 2 + kRunMaxLeaves) * 8, 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
-    const size_t cls_arr = round_up((size_t)ncls * 8, 256);
+    // tile summaries (ver_slot layout: whole verify rounds) and tile prefixes
+    const size_t cls_arr = round_up((size_t)round_up((size_t)ncls, (size_t)kVerRound) * 8, 256);
     Workspace* ws = nullptr;
     // aux: tile offsets, first/last kept keys, kept counts, kept bit masks
     const size_t flag_bytes = round_up((size_t)ncls * (kClsTC / 8), 256);
@@ -2943,7 +2958,7 @@ sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nse
     const size_t ncls = n / kClsTC + 1;
     size_t b = kHdrBytes + round_up((n / 2048 + 2 + kRunMaxLeaves) * 8, 256);
     b += round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
-    b += 4 * round_up(ncls * 8, 256) + round_up(ncls * (kClsTC / 8), 256);
+    b += 4 * round_up(round_up(ncls, (size_t)kVerRound) * 8, 256) + round_up(ncls * (kClsTC / 8), 256);
     b += round_up(ncls * sizeof(RunTile), 256) + round_up(sizeof(RunArea), 256);
     b += round_up((nseg + 1) * 8 * 4, 256);
     *bytes = std::max(b, (size_t)1 << 20);
