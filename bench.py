@@ -249,7 +249,7 @@ def main():
                 roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                             "traffic": measured_traffic("merge_int32_256M"),
-                            "kernel": "merge pass (k_merge int32, 256x16 outputs per workgroup)",
+                            "kernel": "merge pass (k_merge_persist int32, 256x16 outputs per workgroup, nontemporal)",
                             "workload": "int32 random n=268435456",
                             "launch_ms_mean": round(avg_ms, 5), "launches": mcnt,
                             "algorithmic_bytes_per_launch": alg_bytes,
