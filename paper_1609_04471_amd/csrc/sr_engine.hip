@@ -601,7 +601,7 @@ __device__ void run_plan(Ctl* ctl, int64_t n, int64_t ntiles, const typename C::
 // unit j of run [s, e) swaps the pairs (s+p, e-1-p) for p in
 // [j*kRevPairs, (j+1)*kRevPairs) below (e-s)/2, every load before any store.
 template <class S>
-__device__ void runs_reverse(S* keys, const RunArea* ra) {
+__device__ void runs_reverse(S* keys, uint32_t* pay, const RunArea* ra) {
     const long long nrev = ra->nrev, nd = ra->ndesc;
     for (long long u = blockIdx.x; u < nrev; u += gridDim.x) {
         long long lo = 0, hi = nd - 1;
@@ -614,12 +614,17 @@ __device__ void runs_reverse(S* keys, const RunArea* ra) {
         const long long half = (e - s) / 2;
         const long long p0 = (u - ra->dpre[lo]) * kRevPairs;
         S a[kRevPer], b[kRevPer];
+        uint32_t pa[kRevPer], pb[kRevPer];
 #pragma unroll
         for (int r = 0; r < kRevPer; ++r) {
             const long long p = p0 + threadIdx.x + r * kClsWG;
             if (p < half && p < p0 + kRevPairs) {
                 a[r] = keys[s + p];
                 b[r] = keys[e - 1 - p];
+                if (pay != nullptr) {
+                    pa[r] = pay[s + p];
+                    pb[r] = pay[e - 1 - p];
+                }
             }
         }
 #pragma unroll
@@ -628,6 +633,68 @@ __device__ void runs_reverse(S* keys, const RunArea* ra) {
             if (p < half && p < p0 + kRevPairs) {
                 keys[s + p] = b[r];
                 keys[e - 1 - p] = a[r];
+                if (pay != nullptr) {
+                    pay[s + p] = pb[r];
+                    pay[e - 1 - p] = pa[r];
+                }
+            }
+        }
+    }
+}
+
+// Pairs: after runs_reverse every descending run is ascending, with the
+// payloads of each group of equal keys in reversed input order.  Restore it:
+// the payload at i trades places with the one at its mirror inside the group
+// (the stable form of the reversal).  The work is cut into the reversal
+// units; the last unit of an odd run also takes the middle key.
+template <class C>
+__device__ void runs_regroup(const typename C::S* keys, uint32_t* pay, const RunArea* ra) {
+    using U = typename C::U;
+    const long long nrev = ra->nrev, nd = ra->ndesc;
+    for (long long u = blockIdx.x; u < nrev; u += gridDim.x) {
+        long long lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (ra->dpre[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const long long s = ra->ds[lo], e = ra->de[lo];
+        const long long half = (e - s) / 2;
+        const long long p0 = (u - ra->dpre[lo]) * kRevPairs;
+        const bool mid_here = ((e - s) & 1) != 0 && p0 + kRevPairs >= half;
+        for (int r = 0; r < 2 * kRevPer + 1; ++r) {
+            long long i;
+            if (r < 2 * kRevPer) {
+                const long long p = p0 + threadIdx.x + (r >> 1) * kClsWG;
+                if (!(p < half && p < p0 + kRevPairs)) continue;
+                i = (r & 1) ? e - 1 - p : s + p;
+            } else {
+                if (!mid_here || threadIdx.x != 0) continue;
+                i = s + half;
+            }
+            const U x = C::enc(keys[i]);
+            const bool le = i > s && C::enc(keys[i - 1]) == x;
+            const bool re = i + 1 < e && C::enc(keys[i + 1]) == x;
+            if (!le && !re) continue;
+            long long a = s, b = i;  // first key equal to x
+            while (a < b) {
+                const long long m = (a + b) >> 1;
+                if (C::enc(keys[m]) < x) a = m + 1;
+                else b = m;
+            }
+            const long long gs = a;
+            a = i;
+            b = e;  // first key above x
+            while (a < b) {
+                const long long m = (a + b) >> 1;
+                if (C::enc(keys[m]) <= x) a = m + 1;
+                else b = m;
+            }
+            const long long partner = gs + a - 1 - i;
+            if (i < partner) {
+                const uint32_t va = pay[i], vb = pay[partner];
+                pay[i] = vb;
+                pay[partner] = va;
             }
         }
     }
@@ -663,18 +730,20 @@ __device__ __forceinline__ RunChunk run_chunk(const RunArea* ra, int k, long lon
 // RUNS merge pass k with co-ranks from the partition launch (co[c] for every
 // chunk c of the pass), persistent and double-buffered like the general pass.
 template <class MC, class S>
-__device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra, S* U, S* S1, int k,
-                                   const int64_t* co) {
+__device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], const RunArea* ra, S* U, S* S1,
+                                                   uint32_t* PU, uint32_t* PS1, int k, const int64_t* co) {
     if (k >= ra->npasses) return;
     const long long total = ra->ptotal[k];
     const S* src = (k & 1) ? S1 : U;
     S* dst = (k & 1) ? U : S1;
+    const uint32_t* psrc = (k & 1) ? PS1 : PU;  // null for keys-only sorts
+    uint32_t* pdst = (k & 1) ? PU : PS1;
     long long c = blockIdx.x;
     if (c >= total) return;
     typename MC::Win w;
     RunChunk rc = run_chunk(ra, k, c, MC::CH);
     MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
-    MC::load(src + rc.a0, nullptr, w);
+    MC::load(src + rc.a0, psrc ? psrc + rc.a0 : nullptr, w);
     int b = 0;
     for (;;) {
         MC::stage(buf[b], w);
@@ -685,7 +754,7 @@ __device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], c
         if (cn < total) {
             rc = run_chunk(ra, k, cn, MC::CH);
             MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
-            MC::load(src + rc.a0, nullptr, w);
+            MC::load(src + rc.a0, psrc ? psrc + rc.a0 : nullptr, w);
         }
         typename MC::U v[MC::ITEMS];
         uint32_t pv[MC::ITEMS];
@@ -693,7 +762,7 @@ __device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], c
         __syncthreads();
         MC::stage_out(buf[b], cnt, v, pv);
         __syncthreads();
-        MC::store(buf[b], dst + a0, nullptr, out0, cnt);
+        MC::store(buf[b], dst + a0, pdst ? pdst + a0 : nullptr, out0, cnt);
         if (cn >= total) break;
         c = cn;
         b ^= 1;
@@ -702,7 +771,8 @@ __device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], c
 
 // Merge pass k of the RUNS job: chunks of the pass's groups, grid-stride.
 template <class MC, class S>
-__device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, int k) {
+__device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea* ra, S* U, S* S1, uint32_t* PU,
+                                           uint32_t* PS1, int k) {
     if (k >= ra->npasses) return;
     const long long total = ra->ptotal[k];
     const long long* pre = ra->pre + ra->pbase[k];
@@ -710,6 +780,8 @@ __device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea*
     const long long G = (L + (2LL << k) - 1) >> (k + 1);
     const S* src = (k & 1) ? S1 : U;
     S* dst = (k & 1) ? U : S1;
+    const uint32_t* psrc = (k & 1) ? PS1 : PU;  // null for keys-only sorts
+    uint32_t* pdst = (k & 1) ? PU : PS1;
     for (long long c = blockIdx.x; c < total; c += gridDim.x) {
         long long lo = 0, hi = G - 1;
         while (lo < hi) {
@@ -721,8 +793,8 @@ __device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea*
         const long long lm = (l0 + (1LL << k)) < L ? (l0 + (1LL << k)) : L;
         const long long le = (l0 + (2LL << k)) < L ? (l0 + (2LL << k)) : L;
         const long long a0 = ra->lb[l0], mid = ra->lb[lm], e = ra->lb[le];
-        MC::run(sm, src + a0, dst + a0, nullptr, nullptr, e - a0, e - a0, mid - a0, (c - pre[lo]) * MC::CH,
-                nullptr);
+        MC::run(sm, src + a0, dst + a0, psrc ? psrc + a0 : nullptr, pdst ? pdst + a0 : nullptr, e - a0, e - a0,
+                mid - a0, (c - pre[lo]) * MC::CH, nullptr);
         __syncthreads();
     }
 }
@@ -918,7 +990,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename TS::Smem sm;
-    if constexpr (!PAIRS) {
+    if constexpr (TS::T >= kClsTC) {  // the RUNS job needs tiles of whole run-scan tiles
         // RUNS: sort the dense 4096-key tiles of this tile in place, both at
         // once when both are dense (the plan's dense pieces)
         if (ctl != nullptr && rdesc != nullptr && ctl->path == SR_PATH_RUNS) {
@@ -944,12 +1016,12 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
             }
             if (s0 >= 0) {
                 e0 = e0 < n ? e0 : n;
-                TS::run(sm, U + s0, U + s0, nullptr, nullptr, (int)(e0 - s0));
+                TS::run(sm, U + s0, U + s0, PAIRS ? PU + s0 : nullptr, PAIRS ? PU + s0 : nullptr, (int)(e0 - s0));
             }
             if (s1 >= 0) {
                 e1 = e1 < n ? e1 : n;
                 __syncthreads();
-                TS::run(sm, U + s1, U + s1, nullptr, nullptr, (int)(e1 - s1));
+                TS::run(sm, U + s1, U + s1, PAIRS ? PU + s1 : nullptr, PAIRS ? PU + s1 : nullptr, (int)(e1 - s1));
             }
             return;
         }
@@ -1042,13 +1114,13 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
     using S = typename C::S;
     __shared__ typename MC::Smem sm;
     static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
+    if (ctl != nullptr && ra != nullptr && ctl->path == SR_PATH_RUNS) {
+        runs_merge<MC, S>(sm, ra, U, S1, PU, PS1, k);
+        return;
+    }
     if constexpr (!PAIRS) {
         if (ctl != nullptr) {
             const int path = ctl->path;
-            if (ra != nullptr && path == SR_PATH_RUNS) {
-                runs_merge<MC, S>(sm, ra, U, S1, k);
-                return;
-            }
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
                 few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
@@ -1079,13 +1151,13 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         typename MC::Smem c;
     } sm;
     static_assert(sizeof(sm) >= kFewLdsBytes, "fill pass table fits the merge LDS");
+    if (ctl != nullptr && ra != nullptr && ctl->path == SR_PATH_RUNS) {
+        runs_merge_persist<MC, S>(sm.p.b, ra, U, S1, PU, PS1, k, co);
+        return;
+    }
     if constexpr (!PAIRS) {
         if (ctl != nullptr) {
             const int path = ctl->path;
-            if (ra != nullptr && path == SR_PATH_RUNS) {
-                runs_merge_persist<MC, S>(sm.p.b, ra, U, S1, k, co);
-                return;
-            }
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
                 few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
@@ -1326,14 +1398,15 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
 template <class C>
 __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t n, const Ctl* ctl,
                                                     typename C::S* s1, const unsigned int* flags,
-                                                    const unsigned long long* kpref_t, const RunArea* ra) {
+                                                    const unsigned long long* kpref_t, const RunArea* ra,
+                                                    uint32_t* pay) {
     using S = typename C::S;
     constexpr int CP = kClsTC / kClsWG;
     constexpr int NW = kClsTC / 32;  // mask words per tile
     static_assert(NW <= kClsWG, "one word per thread in the scan");
     const int path = ctl->path;
     if (path == SR_PATH_RUNS && ra != nullptr) {
-        runs_reverse<S>(keys, ra);
+        runs_reverse<S>(keys, pay, ra);
         return;
     }
     if (path != SR_PATH_OUTLIER) return;
@@ -1792,8 +1865,13 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
 // are in reversed input order; reverse each group's payloads once more.
 template <class C>
 __global__ __launch_bounds__(kRevWG) void k_regroup(const typename C::S* keys, uint32_t* pay, int64_t n,
-                                                    const Ctl* ctl) {
+                                                    const Ctl* ctl, const RunArea* ra) {
     using U = typename C::U;
+    static_assert(kRevWG == kClsWG, "regroup units are the reversal units");
+    if (ra != nullptr && path_is(ctl, SR_PATH_RUNS)) {
+        runs_regroup<C>(keys, pay, ra);
+        return;
+    }
     if (!path_is(ctl, SR_PATH_REVERSED)) return;
     for (int64_t i = (int64_t)blockIdx.x * kRevWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRevWG) {
         const U x = C::enc(keys[i]);
@@ -2426,7 +2504,9 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     }
     const int64_t nchunks = cdiv(n, CH);
     const bool outlier_ok = !PAIRS && g_outlier_enabled;
-    const bool runs_ok = !PAIRS && g_runs_enabled;
+    // keys-only sorts and pairs with tiles of whole run-scan tiles (the
+    // run reversal of pairs is the stable one)
+    const bool runs_ok = g_runs_enabled && T >= kClsTC;
     const bool few_ok = !PAIRS && g_few_enabled;
     const bool scan_ok = outlier_ok || runs_ok || few_ok;
     const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
@@ -2495,7 +2575,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         }
         ProfScope ps(ls, "scatter");
         hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, keys, n, (const Ctl*)ctl, skeys,
-                           (const unsigned int*)flags, (const unsigned long long*)kpref_t, (const RunArea*)rarea);
+                           (const unsigned int*)flags, (const unsigned long long*)kpref_t, (const RunArea*)rarea,
+                           PAIRS ? pay : nullptr);
         SR_LAUNCH_CHECK("scatter");
     }
     {
@@ -2518,7 +2599,7 @@ tile_done:
         ProfScope ps(ls, "regroup");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n, kRevWG * 4), 8192);
         hipLaunchKernelGGL(k_regroup<C>, dim3(std::max(1u, g)), dim3(kRevWG), 0, ls, (const S*)keys, pay, n,
-                           (const Ctl*)ctl);
+                           (const Ctl*)ctl, (const RunArea*)rarea);
         SR_LAUNCH_CHECK("regroup");
     }
     for (int k = 0; k < M; ++k) {

@@ -195,3 +195,83 @@ def test_runs_random_mix_large(gpu):
     a = np.concatenate(parts).astype(np.int32)
     st = check(gpu, a)
     assert st["path"] == "runs", st
+
+
+# ------------------------------------------------------------------ pairs
+
+from test_gpu_sort import gpu_sort_pairs  # noqa: E402
+
+
+def check_pairs(gpu, k, dtype="int32"):
+    p = np.arange(k.size, dtype=np.uint32)
+    gk, gp = gpu_sort_pairs(gpu, k, p, dtype)
+    wk, wp = oracle.sort_pairs(k, p)
+    assert np.array_equal(bits(gk), bits(wk)) and np.array_equal(gp, wp)
+    return gpu.last_stats()
+
+
+def plateau_runs(n, seed, plateau_p=0.5, max_step=3):
+    """Monotone runs of random directions whose steps are often zero, so the
+    descending runs hold long groups of equal keys."""
+    rng = np.random.default_rng(seed)
+    parts, total = [], 0
+    while total < n:
+        ln = int(rng.integers(2, [50, 5000, 60_000][rng.integers(0, 3)]))
+        steps = rng.integers(1, max_step + 1, size=ln)
+        steps[rng.random(ln) < plateau_p] = 0
+        x = int(rng.integers(-2**20, 2**20)) + np.cumsum(steps)
+        parts.append(x[::-1] if rng.random() < 0.5 else x)
+        total += ln
+    return np.concatenate(parts)[:n].astype(np.int32)
+
+
+@pytest.mark.parametrize("n", [20_000, 300_007, 2_000_000])
+def test_pairs_take_the_run_path_stably(gpu, n):
+    for k in (2, 8, 32):
+        for name in ("equal_teeth", "even_teeth", "sharp_teeth"):
+            st = check_pairs(gpu, inputs.class_int32(name, n, k, seed=k))
+            if n // k >= 3 * 4096:
+                assert st["path"] == "runs", (name, n, k, st)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pairs_plateaus_in_descending_runs(gpu, seed):
+    n = [100_003, 700_001, 3_000_000, 5_000_011][seed]
+    a = plateau_runs(n, seed)
+    st = check_pairs(gpu, a)
+    assert st["path"] in ("runs", "general"), st
+    # long equal groups reversed across unit and tile boundaries
+    b = np.concatenate([np.repeat(np.arange(50, 0, -1), 3001), np.repeat(np.arange(40), 777),
+                        np.repeat(np.arange(30, 0, -1), 9000)]).astype(np.int32)
+    st = check_pairs(gpu, b)
+    assert st["path"] == "runs", st
+
+
+def test_pairs_runs_with_partition_launch_and_dense(gpu):
+    n = 3_000_001
+    a = plateau_runs(n, 11, plateau_p=0.2)
+    a[1_000_000:1_040_000] = inputs.random_int32(40_000, seed=4)   # a disordered stretch
+    gpu.set_option("partition_min_n", 0)
+    try:
+        check_pairs(gpu, a)
+    finally:
+        gpu.set_option("partition_min_n", -1)
+    check_pairs(gpu, a)
+
+
+def test_pairs_runs_float_and_forced(gpu):
+    f = plateau_runs(400_000, 3).astype(np.float32) * np.float32(0.5)
+    f[::1001] = -0.0
+    check_pairs(gpu, f, "float32")
+    a = plateau_runs(300_000, 5)
+    gpu.set_option("force_path", 4)  # SR_PATH_RUNS
+    try:
+        check_pairs(gpu, a)
+        check_pairs(gpu, inputs.random_int32(200_000, seed=1))   # falls back when the plan cannot hold
+    finally:
+        gpu.set_option("force_path", -1)
+    gpu.set_option("runs_path", 0)
+    try:
+        assert check_pairs(gpu, a)["path"] != "runs"
+    finally:
+        gpu.set_option("runs_path", 1)
