@@ -60,8 +60,8 @@ typedef enum {
     SR_PATH_REVERSED = 1,  /* nonincreasing: reversed in place (stable for pairs) */
     SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back */
     SR_PATH_GENERAL = 3,   /* tile sort + merge passes */
-    SR_PATH_RUNS = 4,      /* natural runs (keys, and pairs with 32-bit keys, where
-                              the reversal keeps equal keys in input order):
+    SR_PATH_RUNS = 4,      /* natural runs (keys and pairs; for pairs the reversal
+                              keeps equal keys in input order):
                               descending runs reversed in
                               place, disordered tiles sorted, runs whose values are
                               already in order joined, then a merge tree over the
@@ -260,8 +260,8 @@ const char *sr_last_error_message(void);
  *   "few_path"    1 = keys-only sorts may take SR_PATH_FEW (default); 0 = never.
  *                 A forced SR_PATH_FEW still falls back to SR_PATH_GENERAL when
  *                 more than a quarter of the keys miss the sampled values.
- *   "runs_path"   1 = keys-only sorts, and pairs with 32-bit keys, may take
- *                 SR_PATH_RUNS (default); 0 = never.
+ *   "runs_path"   1 = keys-only and pairs sorts may take SR_PATH_RUNS
+ *                 (default); 0 = never.
  *                 A forced SR_PATH_RUNS still falls back to SR_PATH_GENERAL
  *                 when the run plan exceeds its limits (4096 runs and dense
  *                 pieces, 2048 leaves, half the keys in dense tiles).

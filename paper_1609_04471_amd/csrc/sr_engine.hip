@@ -42,7 +42,9 @@ struct Tune32 {
 };
 template <bool PAIRS>
 struct Tune64 {
-    static constexpr int TWG = 256, TIT = PAIRS ? 8 : 16;
+    // 4096-key tiles either way (whole run-scan tiles, so pairs can take the
+    // run path too); pairs hold 8 keys per thread in registers
+    static constexpr int TWG = PAIRS ? 512 : 256, TIT = PAIRS ? 8 : 16;
     static constexpr int MWG = 256, MIT = 8;
 };
 template <bool PAIRS>

@@ -275,3 +275,13 @@ def test_pairs_runs_float_and_forced(gpu):
         assert check_pairs(gpu, a)["path"] != "runs"
     finally:
         gpu.set_option("runs_path", 1)
+
+
+def test_pairs_runs_uint64(gpu):
+    a = plateau_runs(1_000_003, 7).astype(np.int64)
+    k = (a + (1 << 40)).astype(np.uint64)
+    k[::5003] = np.uint64(2**64 - 1)                 # keys above 2^63
+    st = check_pairs(gpu, k, "uint64")
+    assert st["path"] in ("runs", "general"), st
+    t = inputs.class_int32("even_teeth", 600_000, 6, seed=1).astype(np.int64).astype(np.uint64) << np.uint64(20)
+    assert check_pairs(gpu, t, "uint64")["path"] == "runs"
