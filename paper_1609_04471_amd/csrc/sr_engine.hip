@@ -57,8 +57,11 @@ struct Tune<CodecU64, PAIRS> : Tune64<PAIRS> {};
 constexpr int kProbeWG = 256;
 constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
 constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
+constexpr int kSampleField = 21;       // bits per sampled count in a packed sum
+constexpr unsigned long long kSampleMask = (1ull << kSampleField) - 1;
 constexpr int kRevWG = 256;
 constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over its tiles)
+static_assert(kProbeSample * kProbeMaxGrid < (1 << kSampleField), "packed sample sums fit");
 constexpr unsigned int kProbeGroup = 32;  // probe workgroups per first-level ticket counter
 
 __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
@@ -1632,8 +1635,11 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     const int64_t ntiles = (npairs + kProbeTile - 1) / kProbeTile;
 
     // sample: kProbeSample pairs at the start of tile blockIdx * ntiles / gridDim
-    // sd: sampled descents (low 32 bits) and turning points, where two strict
-    // neighbouring pairs point different ways (high 32 bits)
+    // sd: 21-bit fields (sums over at most 1024 samples of 256 pairs fit):
+    // sampled descents, turning points (two strict neighbouring pairs that
+    // point different ways), and -- added per workgroup below -- the
+    // workgroup's turnings capped at 2, which counts a disordered sample
+    // window like one piece rather than by its many turnings
     unsigned long long sd = 0, sp = 0;
     {
         const int64_t t = (int64_t)blockIdx.x * ntiles / gridDim.x;
@@ -1645,7 +1651,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             sp += x == y ? (1ull << 32) + 1 : 1;  // pairs (low half), equal pairs (high half)
             if (i + 1 < npairs) {
                 const U z = C::enc(keys[i + 2]);
-                if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << 32;
+                if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << kSampleField;
             }
         }
     }
@@ -1722,6 +1728,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             t2 += red[2][w];
             t3 += red[3][w];
         }
+        const unsigned long long wturn = (t2 >> kSampleField) & kSampleMask;
+        t2 += (wturn < 2 ? wturn : 2ull) << (2 * kSampleField);
         // per-workgroup slot (plain stores, no contention), then one ticket
         slots[blockIdx.x * 4 + 0] = d;
         slots[blockIdx.x * 4 + 1] = a;
@@ -1760,18 +1768,24 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             for (int q = 0; q < 4; ++q) tot[q] += red[q][w];
         const unsigned long long desc = tot[0];
         const unsigned long long asc = tot[1];
-        const unsigned long long sdesc = tot[2] & 0xFFFFFFFFull;
-        const unsigned long long sturn = tot[2] >> 32;
+        const unsigned long long sdesc = tot[2] & kSampleMask;
+        const unsigned long long sturn = (tot[2] >> kSampleField) & kSampleMask;
+        const unsigned long long scap = tot[2] >> (2 * kSampleField);
         const unsigned long long spairs = tot[3] & 0xFFFFFFFFull;
         const unsigned long long sequal = tot[3] >> 32;
         const bool mixed = ld_agent(&ctl->mixed) != 0;
         const bool outlier_ok = (jobs_ok & 1) != 0, runs_ok = (jobs_ok & 2) != 0, few_ok = (jobs_ok & 4) != 0;
+        // a run plan is worth a scan when turnings are rare in the sample and
+        // the whole array would not hold clearly more run boundaries (dense
+        // windows counted as pieces) than a plan can
+        const bool runs_like = runs_ok && sturn * 64 <= spairs &&
+                               (double)scap * (double)npairs <= (double)spairs * (2.0 * kRunMaxBase);
         int path;
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
         else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
         else if (outlier_ok && sdesc * 16 <= spairs) path = SR_PATH_OUTLIER;
         else if (few_ok && sequal * 128 >= spairs) path = SR_PATH_FEW;  // confirmed by the sample below
-        else if (runs_ok && sturn * 64 <= spairs) path = SR_PATH_RUNS;
+        else if (runs_like) path = SR_PATH_RUNS;
         else path = SR_PATH_GENERAL;
         const int force = ctl->force_path;
         if (force == SR_PATH_GENERAL || (force == SR_PATH_OUTLIER && outlier_ok) || (force == SR_PATH_RUNS && runs_ok) ||
@@ -1779,10 +1793,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             path = force;
         // fallback if the sample shows too many distinct keys
         s_path = path == SR_PATH_FEW && force != SR_PATH_FEW
-                     ? -((runs_ok && sturn * 64 <= spairs) ? SR_PATH_RUNS : SR_PATH_GENERAL) - 10
+                     ? -(runs_like ? SR_PATH_RUNS : SR_PATH_GENERAL) - 10
                      : path;
         s_force = force == SR_PATH_FEW;
-        s_dual = path == SR_PATH_OUTLIER && runs_ok && force != SR_PATH_OUTLIER && sturn * 64 <= spairs;
+        s_dual = path == SR_PATH_OUTLIER && force != SR_PATH_OUTLIER && runs_like;
         s_desc = desc;
         s_asc = asc;
     }

@@ -253,14 +253,25 @@ struct MergeChunk {
 
     static __device__ __forceinline__ int pad(int e) { return e + (e >> 4); }
 
-    // Window of one chunk: where its inputs are and its loaded elements.
+    // Window of one chunk: where its inputs are and its loaded blocks.
+    // A = src[gA, gA + na) and B = src[gB, gB + cnt - na) are read as the
+    // aligned 16-byte blocks that cover them (RV per thread hold a window of
+    // CH keys however its two parts sit on block boundaries).  A block at a
+    // window edge is read whole: it never crosses a page, so the extra keys it
+    // brings lie in mapped memory, and stage() drops them.  Payloads likewise,
+    // in blocks of four.
+    static constexpr int NBLK = CH / VN + 2;
+    static constexpr int RV = (NBLK + WG - 1) / WG;
+    static constexpr int RVP = PAIRS ? (CH / 4 + 2 + WG - 1) / WG : 1;
     struct Win {
         int64_t out0;   // first output of the chunk (segment-relative)
         int64_t gA;     // first A element of the window (segment-relative)
         int64_t gB;     // first B element of the window
         int na, cnt;
-        S x[IT];
-        uint32_t px[PAIRS ? IT : 1];
+        int offA, offB, nbA, nbB;      // key blocks: elements before gA / gB in their first block; block counts
+        int poffA, poffB, pnbA, pnbB;  // the same for the payload blocks
+        V16<S> x[RV];
+        uint4 px[RVP];
     };
 
     // Runs being merged: pairs of width `width` aligned at multiples of
@@ -319,34 +330,76 @@ struct MergeChunk {
     // Issue every window load of this thread (they stay in flight until stage()).
     // NT: nontemporal loads and stores, for arrays far larger than the caches
     // (the pass's data is not read again before the next pass).
+    template <class T, int TN, bool NT>
+    static __device__ __forceinline__ void load_blocks(const T* base, int64_t gA, int64_t gB, int na, int nb,
+                                                       int& offA, int& offB, int& nbA, int& nbB,
+                                                       V16<T> (&x)[(TN == 0 ? 1 : TN)]) {
+        constexpr int E = 16 / (int)sizeof(T);
+        const uintptr_t pa = (uintptr_t)(base + gA), pb = (uintptr_t)(base + gB);
+        offA = (int)((pa & 15u) / sizeof(T));
+        offB = (int)((pb & 15u) / sizeof(T));
+        nbA = na > 0 ? (offA + na + E - 1) / E : 0;
+        nbB = nb > 0 ? (offB + nb + E - 1) / E : 0;
+        const V16<T>* bA = reinterpret_cast<const V16<T>*>(pa & ~(uintptr_t)15);
+        const V16<T>* bB = reinterpret_cast<const V16<T>*>(pb & ~(uintptr_t)15);
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int r = 0; r < TN; ++r) {
+            const int blk = threadIdx.x + r * WG;
+            const V16<T>* q = blk < nbA ? bA + blk : bB + (blk - nbA);
+            if (blk < nbA + nbB) {
+                if constexpr (NT) {
+                    const v4u t = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(q));
+                    x[r] = *reinterpret_cast<const V16<T>*>(&t);
+                } else {
+                    x[r] = *q;
+                }
+            }
+        }
+    }
+
     template <bool NT = false>
     static __device__ __forceinline__ void load(const S* src, const uint32_t* psrc, Win& w) {
-        const int tid = threadIdx.x;
+        const int nb = w.cnt - w.na;
+        load_blocks<S, RV, NT>(src, w.gA, w.gB, w.na, nb, w.offA, w.offB, w.nbA, w.nbB, w.x);
+        if constexpr (PAIRS) {
+            load_blocks<uint32_t, RVP, NT>(psrc, w.gA, w.gB, w.na, nb, w.poffA, w.poffB, w.pnbA, w.pnbB,
+                                           reinterpret_cast<V16<uint32_t>(&)[RVP]>(w.px));
+        }
+    }
+
+    // The loaded blocks into LDS: A at [0, na), B at [na, cnt), keys encoded.
+    template <class T, int TN, class F>
+    static __device__ __forceinline__ void stage_blocks(const V16<T> (&x)[(TN == 0 ? 1 : TN)], int na, int nb,
+                                                        int offA, int offB, int nbA, int nbB, F&& put) {
+        constexpr int E = 16 / (int)sizeof(T);
 #pragma unroll
-        for (int r = 0; r < IT; ++r) {
-            const int e = tid + r * WG;
-            if (e < w.cnt) {
-                const int64_t gi = e < w.na ? w.gA + e : w.gB + (e - w.na);
-                if constexpr (NT) {
-                    w.x[r] = __builtin_nontemporal_load(src + gi);
-                    if constexpr (PAIRS) w.px[r] = __builtin_nontemporal_load(psrc + gi);
+        for (int r = 0; r < TN; ++r) {
+            const int blk = threadIdx.x + r * WG;
+            if (blk < nbA + nbB) {
+                const bool inA = blk < nbA;
+                const int e0 = inA ? blk * E - offA : (blk - nbA) * E - offB;  // part-relative index of x.v[0]
+                const int lim = inA ? na : nb;
+                const int to = inA ? 0 : na;
+                if (e0 >= 0 && e0 + E <= lim) {
+#pragma unroll
+                    for (int j = 0; j < E; ++j) put(to + e0 + j, x[r].v[j]);
                 } else {
-                    w.x[r] = src[gi];
-                    if constexpr (PAIRS) w.px[r] = psrc[gi];
+#pragma unroll
+                    for (int j = 0; j < E; ++j)
+                        if (e0 + j >= 0 && e0 + j < lim) put(to + e0 + j, x[r].v[j]);
                 }
             }
         }
     }
 
     static __device__ __forceinline__ void stage(Buf& b, const Win& w) {
-        const int tid = threadIdx.x;
-#pragma unroll
-        for (int r = 0; r < IT; ++r) {
-            const int e = tid + r * WG;
-            if (e < w.cnt) {
-                b.k[e] = C::enc(w.x[r]);
-                if constexpr (PAIRS) b.pay[e] = w.px[r];
-            }
+        const int nb = w.cnt - w.na;
+        stage_blocks<S, RV>(w.x, w.na, nb, w.offA, w.offB, w.nbA, w.nbB,
+                            [&](int e, S v) { b.k[e] = C::enc(v); });
+        if constexpr (PAIRS) {
+            stage_blocks<uint32_t, RVP>(reinterpret_cast<const V16<uint32_t>(&)[RVP]>(w.px), w.na, nb, w.poffA,
+                                        w.poffB, w.pnbA, w.pnbB, [&](int e, uint32_t v) { b.pay[e] = v; });
         }
     }
 
