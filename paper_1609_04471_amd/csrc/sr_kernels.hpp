@@ -421,6 +421,27 @@ struct MergeChunk {
             i = lo;
         }
         int j = t0 - i;
+        if constexpr (!PAIRS) {
+            // Keys only: an exhausted run reads as the largest code.  Taking
+            // that stand-in instead of an equal key of the other run writes
+            // the same bits, and every key still to come is then that value
+            // too (both runs are sorted), so the output is exact.
+            constexpr U kMax = ~(U)0;
+            int pa = i, pb = na + j;
+            U a = pa < na ? b.k[pa] : kMax, bb = pb < cnt ? b.k[pb] : kMax;
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const bool ta = a <= bb;
+                v[r] = ta ? a : bb;
+                pa += ta ? 1 : 0;
+                pb += ta ? 0 : 1;
+                const int nx = ta ? pa : pb;        // <= cnt < PADDED: inside the buffer
+                const U kn = nx < (ta ? na : cnt) ? b.k[nx] : kMax;
+                a = ta ? kn : a;
+                bb = ta ? bb : kn;
+            }
+            return;
+        }
         const int last = cnt - 1;
         int ia = i < na ? i : last;
         int ib = na + (j < nb ? j : nb - 1);
@@ -496,6 +517,31 @@ struct MergeChunk {
 
     // One chunk, start to end.  src/dst/psrc/pdst point at the start of the
     // (segment) array of length n; co (optional) holds precomputed co-ranks.
+    // Keys only, a whole chunk into a 16-byte aligned output: each thread
+    // holds IT consecutive outputs and stores them straight from registers.
+    // Returns false (for the whole workgroup alike) where it does not apply.
+    // Not with nontemporal stores: a wavefront's store then writes a quarter
+    // of each of 64 lines, and such partial lines bypass the cache that
+    // would join them (a merge pass at 256M keys took 4x as long).
+    template <bool NT = false>
+    static __device__ __forceinline__ bool store_direct(S* dst, int64_t out0, int cnt, const U (&v)[IT]) {
+        if constexpr (PAIRS || NT) {
+            return false;
+        } else {
+            S* out = dst + out0;
+            if (cnt != CH || !aligned16(out)) return false;
+            V16<S>* q = reinterpret_cast<V16<S>*>(out + threadIdx.x * IT);
+#pragma unroll
+            for (int k = 0; k < IT / VN; ++k) {
+                V16<S> x;
+#pragma unroll
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(v[k * VN + j]);
+                q[k] = x;
+            }
+            return true;
+        }
+    }
+
     static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst,
                                int64_t n, int64_t width, int64_t split, int64_t out0, const int64_t* co) {
         Win w;
@@ -507,6 +553,7 @@ struct MergeChunk {
         U v[IT];
         uint32_t pv[IT];
         merge(sm.b, w.na, w.cnt, v, pv);
+        if (store_direct(dst, out0, w.cnt, v)) return;
         __syncthreads();
         stage_out(sm.b, w.cnt, v, pv);
         __syncthreads();
@@ -551,10 +598,15 @@ struct MergePersistent {
             U v[IT];
             uint32_t pv[IT];
             MC::merge(sm.b[buf], na, cnt, v, pv);
-            __syncthreads();
-            MC::stage_out(sm.b[buf], cnt, v, pv);
-            __syncthreads();
-            MC::template store<NT>(sm.b[buf], dst, pdst, out0, cnt);
+            // the next stage() into this buffer comes after the next
+            // iteration's barrier, which every thread reaches only after
+            // this merge has read it
+            if (!MC::template store_direct<NT>(dst, out0, cnt, v)) {
+                __syncthreads();
+                MC::stage_out(sm.b[buf], cnt, v, pv);
+                __syncthreads();
+                MC::template store<NT>(sm.b[buf], dst, pdst, out0, cnt);
+            }
             if (cn >= nchunks) break;
             c = cn;
             buf ^= 1;
