@@ -1102,7 +1102,8 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
         la = v.split;
         lb = v.n - v.split;
     } else {
-        gs = out0 / (2 * v.width) * (2 * v.width);
+        const int64_t g = 2 * v.width;  // a power of two on level-synchronous passes
+        gs = (g & (g - 1)) == 0 ? (out0 & ~(g - 1)) : out0 / g * g;
         la = (v.n - gs) < v.width ? (v.n - gs) : v.width;
         const int64_t rest = v.n - gs - la;
         lb = rest < v.width ? rest : v.width;

@@ -283,7 +283,10 @@ struct MergeChunk {
             la = split;
             lb = n - split;
         } else {
-            gs = out0 / (2 * width) * (2 * width);
+            // group start; the widths of level-synchronous passes are powers
+            // of two, which spares the 64-bit division
+            const int64_t g = 2 * width;
+            gs = (g & (g - 1)) == 0 ? (out0 & ~(g - 1)) : out0 / g * g;
             la = (n - gs) < width ? (n - gs) : width;
             const int64_t rest = n - gs - la;
             lb = rest < width ? rest : width;
