@@ -149,8 +149,30 @@ sr_status sr_sort_batch(sr_dtype dt, void *const *keys_ptrs, const int64_t *lens
  */
 sr_status sr_reserve(sr_dtype dt, size_t n, size_t nseg, void *stream);
 
+/*
+ * Hands the library a caller-owned device buffer of `bytes` bytes at `buf` as
+ * the data scratch of `stream` on the current device (merge co-ranks, the
+ * partner array of the merge passes, segment plans): later calls on the
+ * stream use it instead of scratch of their own, so an application can
+ * budget, pool or place that memory itself.  buf must be 256-byte aligned and
+ * bytes >= 1 MiB; sr_workspace_bytes gives a sufficient size for a call
+ * shape.  The library keeps a fixed 128 KiB header and the look-back arrays
+ * of the presortedness paths (about 3.5 % of bytes) in memory of its own,
+ * allocated by this call for up to bytes / 4 keys, so a later sort whose
+ * scratch fits allocates nothing; one that does not fit returns
+ * SR_ERR_INVALID_ARGUMENT before it enqueues anything (the keys untouched).
+ * The call synchronizes `stream` and frees data scratch the library held for
+ * it.  buf == NULL gives the scratch back to the library (the next call
+ * allocates its own).  The caller keeps ownership: the buffer must stay
+ * allocated and untouched until the stream has finished its last call and
+ * another buffer, NULL, or sr_release_stream has replaced it.  sr_sort_lists
+ * and sr_measure_presortedness allocate their own extra scratch regardless.
+ */
+sr_status sr_set_workspace(void *buf, size_t bytes, void *stream);
+
 /* Frees the workspace the library holds for `stream` on the current device
- * (after synchronizing it).  Call before destroying a stream that sorted. */
+ * (after synchronizing it; a buffer set by sr_set_workspace is the caller's
+ * and is not freed).  Call before destroying a stream that sorted. */
 sr_status sr_release_stream(void *stream);
 
 /*
@@ -233,7 +255,8 @@ typedef struct {
 sr_status sr_measure_presortedness(sr_dtype dt, const void *keys, size_t n, int32_t flags,
                                    sr_presortedness *out_host, void *stream);
 
-/* Workspace bytes the library would hold for a call of this shape. */
+/* Workspace bytes the library would hold for a call of this shape (an upper
+ * bound; also a sufficient `bytes` for sr_set_workspace). */
 sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nseg, size_t *bytes);
 
 /*

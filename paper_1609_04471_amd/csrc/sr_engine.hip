@@ -2339,6 +2339,7 @@ struct Workspace {
     void* aux = nullptr;
     size_t aux_bytes = 0;
     unsigned long long generation = 0;  // bumped whenever a buffer moves (invalidates captured graphs)
+    bool external = false;              // base is the caller's buffer (sr_set_workspace): never grown or freed
 };
 
 struct LastCall {
@@ -2399,7 +2400,11 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         if (e != hipSuccess) return hip_fail(e, "init");
     }
     const size_t need = round_up(std::max(data_bytes, (size_t)256), 256);
-    if (ws->bytes < need) {
+    if (ws->external) {
+        if (ws->bytes < need)
+            return fail(SR_ERR_INVALID_ARGUMENT, "caller workspace too small: the call needs " + std::to_string(need) +
+                                                     " bytes, " + std::to_string(ws->bytes) + " are set");
+    } else if (ws->bytes < need) {
         if (ws->base) {
             e = hipStreamSynchronize(st);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -2450,6 +2455,18 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
     return SR_OK;
 }
 
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Look-back space of a sort of n keys with every presortedness path on (tile
+// summaries in whole verify rounds, kept-key masks, run descriptors, the run
+// plan): an upper bound of what sort_impl asks for.
+size_t aux_bound(int64_t n) {
+    const size_t ncls = (size_t)cdiv(n, kClsTC);
+    const size_t cls_arr = round_up(round_up(ncls, (size_t)kVerRound) * 8, 256);
+    return 4 * cls_arr + round_up(ncls * (kClsTC / 8), 256) + round_up(ncls * sizeof(RunTile), 256) +
+           round_up(sizeof(RunArea), 256);
+}
+
 void* ws_data(Workspace* ws) { return ws->base; }
 unsigned long long* ws_slots(Workspace* ws) {
     return reinterpret_cast<unsigned long long*>((char*)ws->hdr + kCtlBytes);
@@ -2481,7 +2498,6 @@ int ceil_log2(int64_t x) {
     return r;
 }
 
-int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 #define SR_LAUNCH_CHECK(what)                                  \
     do {                                                       \
@@ -2983,6 +2999,36 @@ sr_status sr_reserve(sr_dtype dt, size_t n, size_t nseg, void* stream) {
     return s;
 }
 
+sr_status sr_set_workspace(void* buf, size_t bytes, void* stream) {
+    g_err.clear();
+    if (buf && ((uintptr_t)buf & 255u)) return fail(SR_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    if (buf && bytes < ((size_t)1 << 20)) return fail(SR_ERR_INVALID_ARGUMENT, "workspace smaller than 1 MiB");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    // no call in flight on the stream may still use the scratch being replaced
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    Workspace* ws;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Workspace*& slot = g_ws[{dev, st}];
+        if (!slot) slot = new Workspace();
+        ws = slot;
+    }
+    if (ws->base && !ws->external) (void)hipFree(ws->base);
+    ws->base = buf;
+    ws->bytes = buf ? bytes : 0;
+    ws->external = buf != nullptr;
+    ws->generation++;
+    if (!buf) return SR_OK;
+    // the header and the look-back space stay the library's: allocate them
+    // now, for the largest sort the buffer can serve (at most bytes / 4 keys)
+    Workspace* w = nullptr;
+    return get_workspace(st, 256, &w, aux_bound((int64_t)(bytes / 4)));
+}
+
 sr_status sr_release_stream(void* stream) {
     g_err.clear();
     hipStream_t st = (hipStream_t)stream;
@@ -3007,7 +3053,7 @@ sr_status sr_release_stream(void* stream) {
     }
     hipError_t e = hipStreamSynchronize(st);
     if (ws->hdr) (void)hipFree(ws->hdr);
-    if (ws->base) (void)hipFree(ws->base);
+    if (ws->base && !ws->external) (void)hipFree(ws->base);
     if (ws->aux) (void)hipFree(ws->aux);
     delete ws;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

@@ -33,7 +33,7 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
            "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
            "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
            "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get",
-           "sr_measure_presortedness", "sr_sort_lists")
+           "sr_measure_presortedness", "sr_sort_lists", "sr_set_workspace")
 SR_MEASURE_INV = 1
 
 # Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
     lib.sr_sort_batch.argtypes = [i32, vp, vp, sz, sz, vp]
     lib.sr_reserve.argtypes = [i32, sz, sz, vp]
     lib.sr_release_stream.argtypes = [vp]
+    lib.sr_set_workspace.argtypes = [vp, sz, vp]
     lib.sr_server_create.argtypes = [ctypes.POINTER(SrServerConfig), ctypes.POINTER(vp)]
     lib.sr_server_submit.argtypes = [vp, i32, vp, sz, ctypes.c_uint64, ctypes.c_double]
     lib.sr_server_now.argtypes = [vp]
@@ -256,6 +257,18 @@ def workspace_bytes(dtype: str, with_payload: bool, n: int, nseg: int = 0) -> in
     _check(lib.sr_workspace_bytes(DTYPES[dtype], int(with_payload), n, nseg, ctypes.byref(b)),
            "sr_workspace_bytes")
     return b.value
+
+
+def set_workspace(buf, stream=None) -> None:
+    """Use the caller's device tensor `buf` (256-byte aligned, >= 1 MiB) as
+    the data scratch of `stream`; None gives the scratch back to the
+    library.  The tensor must outlive every call that uses it."""
+    lib = load()
+    if buf is None:
+        _check(lib.sr_set_workspace(None, 0, _stream(stream)), "sr_set_workspace")
+    else:
+        _check(lib.sr_set_workspace(_dev(buf, "workspace"), buf.numel() * buf.element_size(),
+                                    _stream(stream)), "sr_set_workspace")
 
 
 def set_option(name: str, value: int) -> None:

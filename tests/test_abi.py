@@ -56,6 +56,9 @@ def test_host_side_validation(lib):
     assert lib.sr_sort_keys(0, None, 0, None) == 0
     assert lib.sr_sort_pairs(0, vp(0x1000), None, 10, None) == 1     # NULL payload
     assert lib.sr_sort_pairs(0, vp(0x1000), vp(0x2002), 10, None) == 1
+    assert lib.sr_set_workspace(vp(0x1080), 1 << 20, None) == 1       # not 256-byte aligned
+    assert b"aligned" in lib.sr_last_error_message()
+    assert lib.sr_set_workspace(vp(0x1000), (1 << 20) - 256, None) == 1  # under 1 MiB
     assert lib.sr_set_option(b"no_such_option", 1) == 1
     assert lib.sr_set_option(b"force_path", 9) == 1
     assert lib.sr_set_option(b"profile", 0) == 0
