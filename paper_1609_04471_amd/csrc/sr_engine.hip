@@ -710,16 +710,45 @@ __device__ void runs_regroup(const typename C::S* keys, uint32_t* pay, const Run
 struct RunChunk {
     long long a0, mid, e, out0, first;  // first: index of the group's first chunk
 };
-__device__ __forceinline__ RunChunk run_chunk(const RunArea* ra, int k, long long c, long long CH) {
-    const long long* pre = ra->pre + ra->pbase[k];
-    const long long L = ra->L;
-    const long long G = (L + (2LL << k) - 1) >> (k + 1);
+// Group of chunk c in a pass's chunk prefix: the last g < G with
+// pre[g] <= c (pre[0] = 0, nondecreasing).  Wave form: a 64-ary search that
+// the calling wavefront takes as a whole (every lane, c uniform) -- two
+// dependent rounds for up to 4096 groups where a binary search takes twelve.
+__device__ __forceinline__ long long run_group_wave(const long long* pre, long long G, long long c) {
+    const int lane = (int)__lane_id();
+    long long lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const long long step = (hi - lo + kWave - 1) / kWave;
+        const long long x = lo + 1 + (long long)lane * step;
+        const bool pred = x <= hi && pre[x] <= c;  // true on a prefix of the lanes
+        const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(pred));
+        if (cnt == 0) {
+            hi = lo;
+        } else {
+            const long long nlo = lo + 1 + (long long)(cnt - 1) * step;
+            hi = nlo + step - 1 < hi ? nlo + step - 1 : hi;
+            lo = nlo;
+        }
+    }
+    return lo;
+}
+__device__ __forceinline__ long long run_group_thread(const long long* pre, long long G, long long c) {
     long long lo = 0, hi = G - 1;
     while (lo < hi) {
         const long long mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= c) lo = mid;
         else hi = mid - 1;
     }
+    return lo;
+}
+
+// WAVE: the calling wavefront searches as a whole (c uniform in it).
+template <bool WAVE = false>
+__device__ __forceinline__ RunChunk run_chunk(const RunArea* ra, int k, long long c, long long CH) {
+    const long long* pre = ra->pre + ra->pbase[k];
+    const long long L = ra->L;
+    const long long G = (L + (2LL << k) - 1) >> (k + 1);
+    const long long lo = WAVE ? run_group_wave(pre, G, c) : run_group_thread(pre, G, c);
     const long long l0 = lo << (k + 1);
     const long long lm = (l0 + (1LL << k)) < L ? (l0 + (1LL << k)) : L;
     const long long le = (l0 + (2LL << k)) < L ? (l0 + (2LL << k)) : L;
@@ -746,7 +775,7 @@ __device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], c
     long long c = blockIdx.x;
     if (c >= total) return;
     typename MC::Win w;
-    RunChunk rc = run_chunk(ra, k, c, MC::CH);
+    RunChunk rc = run_chunk<true>(ra, k, c, MC::CH);
     MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
     MC::load(src + rc.a0, psrc ? psrc + rc.a0 : nullptr, w);
     int b = 0;
@@ -757,7 +786,7 @@ __device__ __forceinline__ void runs_merge_persist(typename MC::Buf (&buf)[2], c
         __syncthreads();
         const long long cn = c + gridDim.x;
         if (cn < total) {
-            rc = run_chunk(ra, k, cn, MC::CH);
+            rc = run_chunk<true>(ra, k, cn, MC::CH);
             MC::window_from_co(rc.e - rc.a0, rc.e - rc.a0, rc.mid - rc.a0, rc.out0, co + rc.first, w);
             MC::load(src + rc.a0, psrc ? psrc + rc.a0 : nullptr, w);
         }
@@ -788,12 +817,7 @@ __device__ __forceinline__ void runs_merge(typename MC::Smem& sm, const RunArea*
     const uint32_t* psrc = (k & 1) ? PS1 : PU;  // null for keys-only sorts
     uint32_t* pdst = (k & 1) ? PU : PS1;
     for (long long c = blockIdx.x; c < total; c += gridDim.x) {
-        long long lo = 0, hi = G - 1;
-        while (lo < hi) {
-            const long long mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= c) lo = mid;
-            else hi = mid - 1;
-        }
+        const long long lo = run_group_wave(pre, G, c);
         const long long l0 = lo << (k + 1);
         const long long lm = (l0 + (1LL << k)) < L ? (l0 + (1LL << k)) : L;
         const long long le = (l0 + (2LL << k)) < L ? (l0 + (2LL << k)) : L;
@@ -2653,19 +2677,25 @@ tile_done:
             SR_LAUNCH_CHECK("merge");
         } else {
             ProfScope ps(ls, "merge");
+            // a RUNS pass k cuts each of its <= kRunMaxLeaves / 2^(k+1) groups
+            // into chunks on its own, so it may have that many chunks more
+            // than a level-synchronous pass: one workgroup each, so that no
+            // workgroup merges two chunks one after the other (the extra
+            // workgroups of other jobs return at once)
+            const int64_t extra = runs_ok ? (int64_t)(kRunMaxLeaves >> (k + 1 < 30 ? k + 1 : 30)) + 1 : 0;
             bool done = false;
             if constexpr (sizeof(S) == 4 && !PAIRS && TN::MIT == 16) {
                 if (merge8) {
-                    hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)cdiv(n, TN::MWG * 8)),
+                    hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)(cdiv(n, TN::MWG * 8) + extra)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                        (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab);
                     done = true;
                 }
             }
             if (!done)
-                hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)nchunks), dim3(TN::MWG), 0,
-                                   ls, keys, skeys, pay, spay, n, M, (int64_t)T, k, (const Ctl*)ctl,
-                                   (const RunArea*)rarea, (const FewTable*)ftab);
+                hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)(nchunks + extra)),
+                                   dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
+                                   (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab);
             SR_LAUNCH_CHECK("merge");
         }
     }
