@@ -1641,8 +1641,9 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
 // kProbeTile pairs; a capped grid walks them grid-stride.  Before each tile a
 // workgroup checks the global "mixed" flag and stops once some workgroup has
 // seen both an ascent and a descent (then the array is neither sorted nor
-// reversed).  Each workgroup also samples kProbeSample pairs at an evenly
-// spread position for the descent-rate estimate.  The last workgroup to
+// reversed).  Each workgroup first samples kProbeSample pairs at an evenly
+// spread position for the descent-rate estimate, and skips the tiles at once
+// when its own sample holds both.  The last workgroup to
 // finish turns the counters into the plan and clears them.
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
@@ -1666,12 +1667,15 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     // workgroup's turnings capped at 2, which counts a disordered sample
     // window like one piece rather than by its many turnings
     unsigned long long sd = 0, sp = 0;
+    bool seen_desc = false, seen_asc = false;
     {
         const int64_t t = (int64_t)blockIdx.x * ntiles / gridDim.x;
         const int64_t b0 = t * kProbeTile;
         const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, npairs);
         for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+            seen_desc |= x > y;
+            seen_asc |= x < y;
             sd += x > y ? 1 : 0;
             sp += x == y ? (1ull << 32) + 1 : 1;  // pairs (low half), equal pairs (high half)
             if (i + 1 < npairs) {
@@ -1680,9 +1684,15 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             }
         }
     }
+    // a workgroup whose own sample holds an ascent and a descent already
+    // knows that the array is mixed: it raises the flag and skips the counts
+    const int any_desc = __syncthreads_or((int)seen_desc);
+    const int any_asc = __syncthreads_or((int)seen_asc);
+    const bool sample_mixed = any_desc != 0 && any_asc != 0;
+    if (sample_mixed && tid == 0 && ld_agent(&ctl->mixed) == 0u) atomicOr(&ctl->mixed, 1u);
     unsigned long long d = 0, a = 0;
     const bool vec_ok = aligned16(keys);
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = blockIdx.x; !sample_mixed && t < ntiles; t += gridDim.x) {
         __syncthreads();
         if (tid == 0) skip = ld_agent(&ctl->mixed) != 0;
         __syncthreads();
