@@ -58,10 +58,12 @@ constexpr int kProbeWG = 256;
 constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
 constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
 constexpr int kSampleField = 21;       // bits per sampled count in a packed sum
+constexpr int kAscBits = 40;           // ascent count below the sampled deep drops in one word
 constexpr unsigned long long kSampleMask = (1ull << kSampleField) - 1;
 constexpr int kRevWG = 256;
 constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over its tiles)
 static_assert(kProbeSample * kProbeMaxGrid < (1 << kSampleField), "packed sample sums fit");
+static_assert(kProbeSample * kProbeMaxGrid < (1ll << (64 - kAscBits)), "sampled deep drops fit above the ascents");
 constexpr unsigned int kProbeGroup = 32;  // probe workgroups per first-level ticket counter
 
 __device__ __forceinline__ bool path_is(const Ctl* ctl, int want) {
@@ -75,6 +77,7 @@ constexpr int kClsW = kClsWG * kClsPer;  // 4352-key window
 constexpr int kClsTC = 4096;             // core keys per tile
 constexpr int kClsH = (kClsW - kClsTC) / 2;
 constexpr int kClsMaxIter = 10;  // more rounds: not outlier-shaped (falls back)
+constexpr int kClsDeepIter = 5;  // from this round on, an unrepairable descent ends the rounds
 
 __device__ __forceinline__ int ceil_log2_dev(int64_t x) {
     int r = 0;
@@ -1235,12 +1238,12 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     __shared__ U sk[kClsW];
     __shared__ unsigned int kw[kClsWG], rw[kClsWG];   // per-thread kept masks, removals by others
     __shared__ int wtot[kClsWG / kWave];
-    __shared__ int s_flag[2];
+    __shared__ int s_flag[2], s_both[2];
     __shared__ U s_first, s_last;
     const int tid = threadIdx.x;
     const int lane = (int)__lane_id();
     const int wave = tid / kWave;
-    if (tid < 2) s_flag[tid] = 0;
+    if (tid < 2) s_flag[tid] = s_both[tid] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
     const int64_t ntiles = (n + kClsTC - 1) / kClsTC;
@@ -1330,6 +1333,7 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
         // next two kept keys (read from LDS by position)
         unsigned int own_rem = 0u;
         const bool rem = desc != 0u;
+        bool both = false;
         while (desc != 0u) {
             const int r = __builtin_ctz(desc);
             desc &= desc - 1u;
@@ -1344,7 +1348,10 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
             const U pk = below != 0u ? sk[bj + 31 - __builtin_clz(below)] : (l1 >= 0 ? sk[l1] : (U)0);
             bool ra = !hp || pk <= n1;
             bool rb = !ra && (!h2 || kr <= sk[q2]);
-            if (!ra && !rb) ra = rb = true;
+            if (!ra && !rb) {
+                ra = rb = true;
+                both = true;
+            }
             if (ra) own_rem |= 1u << r;
             if (rb) {
                 if (na >= 1) own_rem |= 1u << (q1 - bj);
@@ -1352,15 +1359,24 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
             }
         }
         if (rem) s_flag[iter & 1] = 1;
+        if (both) s_both[iter & 1] = 1;
         __syncthreads();
         const bool any = s_flag[iter & 1] != 0;
-        if (tid == 0) s_flag[(iter + 1) & 1] = 0;
+        const bool deep = s_both[iter & 1] != 0;
+        if (tid == 0) {
+            s_flag[(iter + 1) & 1] = 0;
+            s_both[(iter + 1) & 1] = 0;
+        }
         km &= ~(own_rem | rw[tid]);
         rw[tid] = 0u;
         if (!any) {
             converged = true;
             break;
         }
+        // a descent that no single removal repairs, still there after
+        // kClsDeepIter rounds, is a boundary between overlapping runs being
+        // peeled key by key: the tile is not outlier-shaped
+        if (deep && iter >= kClsDeepIter) break;
     }
     // the final kept masks, for the core pass below
     kw[tid] = km;
@@ -1647,12 +1663,13 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
 // finish turns the counters into the plan and clears them.
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
-                                                    unsigned long long* slots, int jobs_ok, FewTable* ft) {
+                                                    unsigned long long* slots, int jobs_ok, int runs_pmax,
+                                                    FewTable* ft) {
     using U = typename C::U;
     using S = typename C::S;
     constexpr int VN = 16 / sizeof(S);
     constexpr int Q = (int)(kProbeTile / (kProbeWG * VN));  // vectors per thread per tile
-    __shared__ unsigned long long red[4][kProbeWG / kWave];
+    __shared__ unsigned long long red[5][kProbeWG / kWave];
     __shared__ int skip;
     __shared__ unsigned int last;
     const int tid = threadIdx.x;
@@ -1660,27 +1677,44 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     const int64_t npairs = n - 1;
     const int64_t ntiles = (npairs + kProbeTile - 1) / kProbeTile;
 
-    // sample: kProbeSample pairs at the start of tile blockIdx * ntiles / gridDim
+    // sample: kProbeSample pairs around tile blockIdx * ntiles / gridDim, at an
+    // offset scattered by a multiplicative hash of the workgroup index (so
+    // that boundaries of inputs built on powers of two, such as tile-aligned
+    // ones, are hit as often as any others)
     // sd: 21-bit fields (sums over at most 1024 samples of 256 pairs fit):
     // sampled descents, turning points (two strict neighbouring pairs that
     // point different ways), and -- added per workgroup below -- the
     // workgroup's turnings capped at 2, which counts a disordered sample
-    // window like one piece rather than by its many turnings
-    unsigned long long sd = 0, sp = 0;
+    // window like one piece rather than by its many turnings.
+    // sp: 21-bit fields: pairs, equal pairs, and hard valleys -- valleys
+    // x > y < z with x > z, where the stretches on the two sides overlap in
+    // value, so that no run plan can join the runs they end and start (kept
+    // only for windows with few turnings, below).
+    // sdd: deep drops -- descents x > y between two ascending stretches
+    // (w <= x, y <= z) that removing x or y alone does not repair (w > y and
+    // x > z): a boundary between overlapping runs, which the outlier split
+    // would have to peel off key by key.
+    unsigned long long sd = 0, sp = 0, sdd = 0;
     bool seen_desc = false, seen_asc = false;
     {
         const int64_t t = (int64_t)blockIdx.x * ntiles / gridDim.x;
-        const int64_t b0 = t * kProbeTile;
+        int64_t b0 = t * kProbeTile + (int64_t)((blockIdx.x * 2654435761u) % (unsigned)kProbeTile) - kProbeSample / 2;
+        b0 = std::max<int64_t>(0, std::min<int64_t>(b0, npairs - kProbeSample));
         const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, npairs);
         for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
             seen_desc |= x > y;
             seen_asc |= x < y;
             sd += x > y ? 1 : 0;
-            sp += x == y ? (1ull << 32) + 1 : 1;  // pairs (low half), equal pairs (high half)
+            sp += x == y ? (1ull << kSampleField) + 1 : 1;
             if (i + 1 < npairs) {
                 const U z = C::enc(keys[i + 2]);
                 if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << kSampleField;
+                if (x > y && y < z && x > z) sp += 1ull << (2 * kSampleField);
+                if (x > y && y <= z && x > z && i > 0) {
+                    const U w = C::enc(keys[i - 1]);
+                    sdd += (w <= x && w > y) ? 1 : 0;
+                }
             }
         }
     }
@@ -1752,22 +1786,30 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     __syncthreads();
     sd = wave_sum(sd);
     sp = wave_sum(sp);
+    sdd = wave_sum(sdd);
     if (__lane_id() == 0) {
         red[2][wave] = sd;
         red[3][wave] = sp;
+        red[4][wave] = sdd;
     }
     __syncthreads();
     if (tid == 0) {
-        unsigned long long t2 = 0, t3 = 0;
+        unsigned long long t2 = 0, t3 = 0, t4 = 0;
         for (int w = 0; w < kProbeWG / kWave; ++w) {
             t2 += red[2][w];
             t3 += red[3][w];
+            t4 += red[4][w];
         }
         const unsigned long long wturn = (t2 >> kSampleField) & kSampleMask;
         t2 += (wturn < 2 ? wturn : 2ull) << (2 * kSampleField);
-        // per-workgroup slot (plain stores, no contention), then one ticket
+        // hard valleys count only in windows that look like runs (at most two
+        // turnings); a disordered window becomes one dense piece of a plan
+        if (wturn > 2) t3 &= (1ull << (2 * kSampleField)) - 1;
+        // per-workgroup slot (plain stores, no contention), then one ticket;
+        // the ascent count (at most n <= 2^36 over all slots) shares its word
+        // with the deep drops (bits kAscBits and up)
         slots[blockIdx.x * 4 + 0] = d;
-        slots[blockIdx.x * 4 + 1] = a;
+        slots[blockIdx.x * 4 + 1] = a + (t4 << kAscBits);
         slots[blockIdx.x * 4 + 2] = t2;
         slots[blockIdx.x * 4 + 3] = t3;
         __threadfence();
@@ -1802,23 +1844,33 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         for (int w = 0; w < kProbeWG / kWave; ++w)
             for (int q = 0; q < 4; ++q) tot[q] += red[q][w];
         const unsigned long long desc = tot[0];
-        const unsigned long long asc = tot[1];
+        const unsigned long long asc = tot[1] & ((1ull << kAscBits) - 1);
+        const unsigned long long sdrop = tot[1] >> kAscBits;
         const unsigned long long sdesc = tot[2] & kSampleMask;
         const unsigned long long sturn = (tot[2] >> kSampleField) & kSampleMask;
         const unsigned long long scap = tot[2] >> (2 * kSampleField);
-        const unsigned long long spairs = tot[3] & 0xFFFFFFFFull;
-        const unsigned long long sequal = tot[3] >> 32;
+        const unsigned long long spairs = tot[3] & kSampleMask;
+        const unsigned long long sequal = (tot[3] >> kSampleField) & kSampleMask;
+        const unsigned long long shard = tot[3] >> (2 * kSampleField);
         const bool mixed = ld_agent(&ctl->mixed) != 0;
         const bool outlier_ok = (jobs_ok & 1) != 0, runs_ok = (jobs_ok & 2) != 0, few_ok = (jobs_ok & 4) != 0;
-        // a run plan is worth a scan when turnings are rare in the sample and
-        // the whole array would not hold clearly more run boundaries (dense
-        // windows counted as pieces) than a plan can
-        const bool runs_like = runs_ok && sturn * 64 <= spairs &&
+        // a run plan is worth a scan when turnings are rare in the sample, the
+        // whole array would not hold clearly more run boundaries (dense
+        // windows counted as pieces) than a plan can, and the leaves that the
+        // hard valleys alone force (scaled to the array; trusted from four
+        // sampled ones on) leave merge passes enough to save over the general
+        // path to pay for the scan and plan
+        const double hard = (double)shard * (double)npairs / (double)(spairs ? spairs : 1);
+        const bool runs_pay = shard < 4 || ceil_log2_dev((int64_t)hard + 1) <= runs_pmax;
+        const bool runs_like = runs_ok && sturn * 64 <= spairs && runs_pay &&
                                (double)scap * (double)npairs <= (double)spairs * (2.0 * kRunMaxBase);
+        // the outlier split repairs descents a few keys deep; when most
+        // sampled descents are deep drops it would only fall back
+        const bool drops = sdrop * 2 > sdesc;
         int path;
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
         else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
-        else if (outlier_ok && sdesc * 16 <= spairs) path = SR_PATH_OUTLIER;
+        else if (outlier_ok && sdesc * 16 <= spairs && !drops) path = SR_PATH_OUTLIER;
         else if (few_ok && sequal * 128 >= spairs) path = SR_PATH_FEW;  // confirmed by the sample below
         else if (runs_like) path = SR_PATH_RUNS;
         else path = SR_PATH_GENERAL;
@@ -2246,6 +2298,12 @@ sr_status hip_fail(hipError_t e, const char* what) {
 }
 
 std::mutex g_mu;
+// device-time model behind the probe's run-scan gate (measured on gfx950:
+// the scan, the outlier rounds it can bring along and the plan together
+// against a merge pass at 2M .. 32M keys)
+constexpr double kRunScanUs = 40.0;
+constexpr double kPassFloorUs = 8.0;
+
 int g_force_path = -1;
 bool g_profile = false;
 bool g_outlier_enabled = true;  // allow the OUTLIER path for keys-only sorts
@@ -2611,8 +2669,15 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     {
         ProfScope ps(ls, "probe");
         const unsigned g = (unsigned)std::min<int64_t>(cdiv(n - 1, kProbeTile), kProbeMaxGrid);
+        // a run scan and plan cost about kRunScanUs of device time; a merge
+        // pass costs a launch-bound floor plus its HBM time (about 5.5 TB/s):
+        // the scan pays only if the plan's leaves leave at least that many
+        // passes saved, so the leaves the probe sees forced may merge in at
+        // most runs_pmax passes
+        const double pass_us = kPassFloorUs + (double)n * (double)(sizeof(S) + (PAIRS ? 4 : 0)) * 2.0 / 5.5e6;
+        const int runs_pmax = M - (int)std::ceil(kRunScanUs / pass_us);
         hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
-                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0), ftab);
+                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0), runs_pmax, ftab);
         SR_LAUNCH_CHECK("probe");
     }
     if (scan_ok) {
