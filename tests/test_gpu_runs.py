@@ -285,3 +285,20 @@ def test_pairs_runs_uint64(gpu):
     assert st["path"] in ("runs", "general"), st
     t = inputs.class_int32("even_teeth", 600_000, 6, seed=1).astype(np.int64).astype(np.uint64) << np.uint64(20)
     assert check_pairs(gpu, t, "uint64")["path"] == "runs"
+
+
+def test_probe_skips_run_scans_that_cannot_pay(gpu):
+    """Hard valleys (runs overlapping in value, never joined) seen in the
+    probe's sample bound the plan's leaves from below: 1024 equal teeth in 2M
+    keys need more merge passes than a scan can save, so the probe goes
+    straight to the general path; their tooth boundaries are deep drops, so
+    the outlier split is not tried either.  Sharp teeth have as many runs
+    but no hard valleys (every run continues the previous one): still RUNS."""
+    n = 2_000_000
+    st = check(gpu, inputs.class_int32("equal_teeth", n, 1024, seed=1))
+    assert st["path"] == "general", st
+    st = check(gpu, inputs.class_int32("sharp_teeth", n, 1024, seed=1))
+    assert st["path"] == "runs" and st["merge_passes"] == 0, st
+    # few teeth: the scan pays, and without the outlier attempt
+    st = check(gpu, inputs.class_int32("equal_teeth", 1 << 23, 128, seed=1))
+    assert st["path"] == "runs", st
