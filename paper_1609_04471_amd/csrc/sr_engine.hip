@@ -1687,9 +1687,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     // workgroup's turnings capped at 2, which counts a disordered sample
     // window like one piece rather than by its many turnings.
     // sp: 21-bit fields: pairs, equal pairs, and hard valleys -- valleys
-    // x > y < z with x > z, where the stretches on the two sides overlap in
-    // value, so that no run plan can join the runs they end and start (kept
-    // only for windows with few turnings, below).
+    // x > y < z (or x > y = z < u) with x >= z (x >= u), where the stretches
+    // on the two sides overlap in value, so that a run plan cannot join the
+    // runs they end and start (kept only for windows with few turnings,
+    // below).
     // sdd: deep drops -- descents x > y between two ascending stretches
     // (w <= x, y <= z) that removing x or y alone does not repair (w > y and
     // x > z): a boundary between overlapping runs, which the outlier split
@@ -1710,7 +1711,12 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             if (i + 1 < npairs) {
                 const U z = C::enc(keys[i + 2]);
                 if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << kSampleField;
-                if (x > y && y < z && x > z) sp += 1ull << (2 * kSampleField);
+                if (x > y && y < z && x >= z) {
+                    sp += 1ull << (2 * kSampleField);
+                } else if (x > y && y == z && i + 2 < npairs) {  // a valley on a plateau of two
+                    const U u = C::enc(keys[i + 3]);
+                    if (y < u && x >= u) sp += 1ull << (2 * kSampleField);
+                }
                 if (x > y && y <= z && x > z && i > 0) {
                     const U w = C::enc(keys[i - 1]);
                     sdd += (w <= x && w > y) ? 1 : 0;
