@@ -278,3 +278,59 @@ def test_tuning_variants_same_bytes(gpu, tile_variant, merge_items):
     finally:
         gpu.set_option("tile_variant", -1)
         gpu.set_option("merge_items", 0)
+
+
+def test_concurrent_host_threads(gpu):
+    """Four host threads sort on four streams at once (ctypes drops the GIL
+    during each call): keys and pairs of every kind and ragged sizes, each
+    result bit-exact against the oracle."""
+    import threading
+    cases = []
+    for t in range(4):
+        mine = []
+        for j, kind in enumerate(inputs.TYPES):
+            n = [70_001, 300_007, 1_000_003][(t + j) % 3]
+            a = inputs.int32_of_type(kind, n, 100 * t + j)
+            mine.append(("keys", a, None, oracle.sort_keys(a)))
+        k, p = inputs.runs_uint64(200_003, seed=60 + t, tie_stress=True)
+        mine.append(("pairs", k, p, oracle.sort_pairs(k, p)))
+        cases.append(mine)
+    dev = [[(to_dev(a), to_dev(p.view(np.int32)) if p is not None else None) for _, a, p, _ in mine]
+           for mine in cases]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    errors = []
+
+    def worker(t):
+        try:
+            st = streams[t]
+            for rep in range(3):
+                for (what, a, p, _), (tk, tp) in zip(cases[t], dev[t]):
+                    if rep:  # restore the input on this stream, then sort again
+                        with torch.cuda.stream(st):
+                            tk.copy_(to_dev(a))
+                            if tp is not None:
+                                tp.copy_(to_dev(p.view(np.int32)))
+                    if what == "keys":
+                        gpu.sort_keys(tk, dtype="int32", stream=st)
+                    else:
+                        gpu.sort_pairs(tk, tp, dtype="uint64", stream=st)
+            st.synchronize()
+        except Exception as e:  # reported by the main thread
+            errors.append((t, repr(e)))
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for mine, dv in zip(cases, dev):
+        for (what, a, p, want), (tk, tp) in zip(mine, dv):
+            if what == "keys":
+                assert np.array_equal(bits(from_dev(tk, a)), bits(want)), (what, a.size)
+            else:
+                assert np.array_equal(bits(from_dev(tk, a)), bits(want[0]))
+                assert np.array_equal(from_dev(tp, p), want[1])
+    for st in streams:
+        assert gpu.load().sr_release_stream(st.cuda_stream) == 0
