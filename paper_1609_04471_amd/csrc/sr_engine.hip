@@ -1897,51 +1897,106 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         __syncthreads();
         int path = s_path;
         if (path == SR_PATH_FEW || path <= -10) {
-            // FEW: the distinct keys of kFewSample evenly spread samples,
-            // sorted by the tile sorter (256 threads x 4 keys) in a scratch
-            // row of the table, become the splitters if there are at most
-            // kFewMax of them (or, when forced, the first kFewMax)
-            using FS = TileSort<C, kProbeWG, kFewSample / kProbeWG, false>;
-            static_assert(FS::T == kFewSample, "one sample tile");
-            __shared__ typename FS::Smem fsm;
-            __shared__ int s_cnt[kProbeWG / kWave];
-            S* samp = reinterpret_cast<S*>(ft->sample);
-            for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[(int64_t)i * n / kFewSample];
-            __syncthreads();
-            FS::run(fsm, samp, samp, nullptr, nullptr, kFewSample);
-            __syncthreads();
+            // FEW: the distinct values among kFewSample evenly spread samples
+            // become the splitters if there are at most kFewMax of them.  They
+            // are counted in an LDS hash set (open addressing; a slot holds
+            // the encoded key + 1, 0 for empty, and is claimed by one
+            // compare-and-swap per probe, so no lane ever waits on another;
+            // the 64-bit largest code, whose key + 1 wraps to 0, is a flag)
+            // and, when few enough, sorted by one wavefront.  A forced FEW
+            // with more distinct samples takes the kFewMax smallest, from the
+            // sample sorted by the tile sorter.
             constexpr int PER = kFewSample / kProbeWG;
-            int c = 0;
-            bool first[PER];
-            U cur[PER];
-            U prv = tid > 0 ? C::enc(samp[tid * PER - 1]) : (U)0;
+            constexpr int HB = 11, HS = 1 << HB;
+            static_assert(HS >= 2 * kFewSample, "the hash set stays at most half full");
+            static_assert(kFewMax <= kWave, "one splitter per lane");
+            __shared__ unsigned long long hset[HS];
+            __shared__ unsigned long long hval[kFewMax];
+            __shared__ int s_dist, s_top, s_nv;
+            for (int i = tid; i < HS; i += kProbeWG) hset[i] = 0ull;
+            if (tid == 0) {
+                s_dist = 0;
+                s_top = 0;
+                s_nv = 0;
+            }
+            U sv[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) sv[r] = C::enc(keys[(int64_t)(tid * PER + r) * n / kFewSample]);
+            __syncthreads();
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
-                const int i = tid * PER + r;
-                cur[r] = C::enc(samp[i]);
-                first[r] = i == 0 || cur[r] != prv;
-                prv = cur[r];
-                c += first[r] ? 1 : 0;
+                const unsigned long long code = (unsigned long long)sv[r] + 1ull;
+                if (code == 0ull) {
+                    s_top = 1;
+                    continue;
+                }
+                unsigned int h = (unsigned int)((code * 0x9E3779B97F4A7C15ull) >> (64 - HB));
+                for (;;) {  // ends: at most kFewSample of the HS slots are ever taken
+                    const unsigned long long old = atomicCAS(&hset[h], 0ull, code);
+                    if (old == 0ull) {
+                        atomicAdd(&s_dist, 1);
+                        break;
+                    }
+                    if (old == code) break;
+                    h = (h + 1u) & (HS - 1);
+                }
             }
-            int xc = c;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int y = __shfl_up(xc, o);
-                if ((int)__lane_id() >= o) xc += y;
-            }
-            if (__lane_id() == kWave - 1) s_cnt[wave] = xc;
             __syncthreads();
-            int total = 0, pre = xc - c;
-            for (int w = 0; w < kProbeWG / kWave; ++w) {
-                total += s_cnt[w];
-                if (w < wave) pre += s_cnt[w];
-            }
-            const bool take = total <= kFewMax || s_force;
-            if (take) {
+            const int total = s_dist + s_top;
+            int ns = -1;  // splitters taken; -1: not few-unique
+            if (total <= kFewMax) {
+                for (int i = tid; i < HS; i += kProbeWG) {
+                    const unsigned long long c = hset[i];
+                    if (c != 0ull) hval[atomicAdd(&s_nv, 1)] = c - 1ull;
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    // padding with the largest code keeps the real values first
+                    const int lane = (int)__lane_id();
+                    U v[1] = {lane < s_dist ? (U)hval[lane] : (U)~(U)0};
+                    wave_sort(v);
+                    if (lane < total) ft->split[lane] = (unsigned long long)v[0];
+                }
+                ns = total;
+            } else if (s_force) {
+                using FS = TileSort<C, kProbeWG, kFewSample / kProbeWG, false>;
+                static_assert(FS::T == kFewSample, "one sample tile");
+                __shared__ typename FS::Smem fsm;
+                __shared__ int s_cnt[kProbeWG / kWave];
+                S* samp = reinterpret_cast<S*>(ft->sample);
+                for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[(int64_t)i * n / kFewSample];
+                __syncthreads();
+                FS::run(fsm, samp, samp, nullptr, nullptr, kFewSample);
+                __syncthreads();
+                int c = 0;
+                bool first[PER];
+                U cur[PER];
+                U prv = tid > 0 ? C::enc(samp[tid * PER - 1]) : (U)0;
+#pragma unroll
+                for (int r = 0; r < PER; ++r) {
+                    const int i = tid * PER + r;
+                    cur[r] = C::enc(samp[i]);
+                    first[r] = i == 0 || cur[r] != prv;
+                    prv = cur[r];
+                    c += first[r] ? 1 : 0;
+                }
+                int xc = c;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int y = __shfl_up(xc, o);
+                    if ((int)__lane_id() >= o) xc += y;
+                }
+                if (__lane_id() == kWave - 1) s_cnt[wave] = xc;
+                __syncthreads();
+                int pre = xc - c;
+                for (int w = 0; w < wave; ++w) pre += s_cnt[w];
 #pragma unroll
                 for (int r = 0; r < PER; ++r)
                     if (first[r] && pre < kFewMax) ft->split[pre++] = (unsigned long long)cur[r];
-                const int ns = total < kFewMax ? total : kFewMax;
+                ns = kFewMax;
+            }
+            __syncthreads();
+            if (ns >= 0) {
                 for (int b = tid; b < kFewCopies * (2 * ns + 1); b += kProbeWG)
                     ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)] = 0;
                 if (tid == 0) ft->ns = (unsigned long long)ns;
