@@ -92,14 +92,17 @@ typedef struct {
  * ascending order of Sec. 1; equal keys are bit-identical, so the result is
  * the unique sorted permutation.
  * Errors: SR_ERR_INVALID_ARGUMENT for keys == NULL with n > 1, a bad dtype or
- * a misaligned pointer.
+ * a misaligned pointer; SR_ERR_UNSUPPORTED when `stream` is capturing into a
+ * graph (plain sorts are launched directly; sr_sort_segmented has a graph
+ * option of its own), before anything is enqueued.
  */
 sr_status sr_sort_keys(sr_dtype dt, void *keys, size_t n, void *stream);
 
 /*
  * Stable sort of (key, payload) records in place: keys at `keys` (type dt),
  * payload[i] travels with keys[i].  Among equal keys the input order is kept
- * (Sec. 3 (a), Sec. 6).  payload must not be NULL when n > 1.
+ * (Sec. 3 (a), Sec. 6).  payload must not be NULL when n > 1.  Errors as
+ * sr_sort_keys.
  */
 sr_status sr_sort_pairs(sr_dtype dt, void *keys, uint32_t *payload, size_t n, void *stream);
 

@@ -2664,6 +2664,16 @@ template <class C, bool PAIRS>
 sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool prepare_only = false,
                     hipStream_t ls = nullptr) {
     if (ls == nullptr) ls = st;
+    {
+        // a plain sort recorded into the caller's stream capture would be
+        // replayed by the graph executor, whose replays of this launch
+        // sequence were not reliable here: refuse it before anything is
+        // enqueued (the segmented entry point captures its own graphs)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            return fail(SR_ERR_UNSUPPORTED, "plain sorts cannot be recorded into a stream capture; "
+                                            "sr_sort_segmented with the graph option captures its own graph");
+    }
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
     constexpr int T = TN::TWG * TN::TIT;

@@ -334,3 +334,30 @@ def test_concurrent_host_threads(gpu):
                 assert np.array_equal(from_dev(tp, p), want[1])
     for st in streams:
         assert gpu.load().sr_release_stream(st.cuda_stream) == 0
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")  # nothing was recorded: the point
+def test_plain_sort_refuses_stream_capture(gpu):
+    """A plain sort on a stream that is capturing into a graph is refused
+    with SR_ERR_UNSUPPORTED before anything is recorded; the keys stay as
+    they were and the same call sorts once the capture has ended."""
+    lib = gpu.load()
+    a = inputs.random_int32(100_003, seed=21)
+    t = to_dev(a)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        g.capture_begin()
+        try:
+            rc = lib.sr_sort_keys(0, t.data_ptr(), a.size, st.cuda_stream)
+            rc_pairs = lib.sr_sort_pairs(0, t.data_ptr(), t.data_ptr(), a.size, st.cuda_stream)
+        finally:
+            g.capture_end()
+    assert rc == 2 and rc_pairs == 2, (rc, rc_pairs)
+    assert b"capture" in lib.sr_last_error_message()
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(t, a), a)
+    gpu.sort_keys(t, dtype="int32", stream=st)
+    st.synchronize()
+    assert np.array_equal(from_dev(t, a), np.sort(a))
