@@ -93,8 +93,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build sorts on one GPU; a run over several GPUs is not part of it "
-              "(see DESIGN.md for how the sort would shard).", file=sys.stderr)
+        print("bench.py: libsortrace sorts on one GPU; runs over several GPUs are not supported "
+              "(a sharded sort would sort each GPU's share, exchange key ranges once at rank "
+              "splitters and merge what each GPU receives).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
