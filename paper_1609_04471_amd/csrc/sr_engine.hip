@@ -1863,11 +1863,11 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         // a run plan is worth a scan when turnings are rare in the sample, the
         // whole array would not hold clearly more run boundaries (dense
         // windows counted as pieces) than a plan can, and the leaves that the
-        // hard valleys alone force (scaled to the array; trusted from four
+        // hard valleys alone force (scaled to the array; trusted from two
         // sampled ones on) leave merge passes enough to save over the general
         // path to pay for the scan and plan
         const double hard = (double)shard * (double)npairs / (double)(spairs ? spairs : 1);
-        const bool runs_pay = shard < 4 || ceil_log2_dev((int64_t)hard + 1) <= runs_pmax;
+        const bool runs_pay = shard < 2 || ceil_log2_dev((int64_t)hard + 1) <= runs_pmax;
         const bool runs_like = runs_ok && sturn * 64 <= spairs && runs_pay &&
                                (double)scap * (double)npairs <= (double)spairs * (2.0 * kRunMaxBase);
         // the outlier split repairs descents a few keys deep; when most
