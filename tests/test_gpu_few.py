@@ -115,3 +115,32 @@ def test_forced_and_switched_off(gpu):
         assert check(gpu, b)["path"] == "general"
     finally:
         gpu.set_option("few_path", 1)
+
+
+@pytest.mark.parametrize("distinct,few", [(64, True), (65, False)])
+def test_distinct_count_limit(gpu, distinct, few):
+    """The probe keeps FEW for at most 64 distinct sampled values: 64 values
+    spread evenly (every one sampled) take the bucket pass, 65 do not."""
+    n = 1_000_003
+    rng = np.random.default_rng(distinct)
+    vals = np.unique(rng.integers(-2**31, 2**31, size=4 * distinct, dtype=np.int64))[:distinct]
+    assert vals.size == distinct
+    a = vals[rng.integers(0, distinct, size=n)].astype(np.int32)
+    st = check(gpu, a, "int32")
+    assert (st["path"] == "few") == few, st
+
+
+def test_extreme_codes_in_the_sample(gpu):
+    """Values whose order codes are the smallest and largest of their type --
+    for uint64 the largest code has no code + 1 and is counted apart -- are
+    found by the sample and become splitters like any other."""
+    n = 800_011
+    rng = np.random.default_rng(12)
+    vals = np.array([0, 2**64 - 1, 5, 2**63, 2**63 - 1, 77], dtype=np.uint64)
+    u = vals[rng.integers(0, vals.size, size=n)]
+    st = check(gpu, u, "uint64")
+    assert st["path"] == "few", st
+    ivals = np.array([-2**31, 2**31 - 1, 0, -1, 1], dtype=np.int32)
+    a = ivals[rng.integers(0, ivals.size, size=n)]
+    st = check(gpu, a, "int32")
+    assert st["path"] == "few", st
