@@ -59,6 +59,7 @@ constexpr int64_t kProbeTile = 8192;   // keys per probe workgroup
 constexpr int kProbeSample = 256;      // neighbour pairs sampled per probe workgroup
 constexpr int kSampleField = 21;       // bits per sampled count in a packed sum
 constexpr int kAscBits = 40;           // ascent count below the sampled deep drops in one word
+constexpr int64_t kDropDepth = 16;     // a deep drop's overlap reaches at least this far
 constexpr unsigned long long kSampleMask = (1ull << kSampleField) - 1;
 constexpr int kRevWG = 256;
 constexpr int64_t kProbeMaxGrid = 1024; // probe workgroups (grid-stride over its tiles)
@@ -1693,8 +1694,9 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     // below).
     // sdd: deep drops -- descents x > y between two ascending stretches
     // (w <= x, y <= z) that removing x or y alone does not repair (w > y and
-    // x > z): a boundary between overlapping runs, which the outlier split
-    // would have to peel off key by key.
+    // x > z), with the stretch after them still below x kDropDepth keys on:
+    // a boundary between runs that overlap further than the outlier split
+    // can peel off in its rounds (a short displaced block is not one).
     unsigned long long sd = 0, sp = 0, sdd = 0;
     bool seen_desc = false, seen_asc = false;
     {
@@ -1717,9 +1719,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                     const U u = C::enc(keys[i + 3]);
                     if (y < u && x >= u) sp += 1ull << (2 * kSampleField);
                 }
-                if (x > y && y <= z && x > z && i > 0) {
+                if (x > y && y <= z && x > z && i > 0 && i + 1 + kDropDepth < n) {
                     const U w = C::enc(keys[i - 1]);
-                    sdd += (w <= x && w > y) ? 1 : 0;
+                    const U far = C::enc(keys[i + 1 + kDropDepth]);
+                    sdd += (w <= x && w > y && far < x) ? 1 : 0;
                 }
             }
         }

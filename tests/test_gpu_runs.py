@@ -302,3 +302,20 @@ def test_probe_skips_run_scans_that_cannot_pay(gpu):
     # few teeth: the scan pays, and without the outlier attempt
     st = check(gpu, inputs.class_int32("equal_teeth", 1 << 23, 128, seed=1))
     assert st["path"] == "runs", st
+
+
+@pytest.mark.parametrize("n", [300_007, 2_000_000])
+def test_displaced_blocks_and_the_outlier_split(gpu, n):
+    """Sorted keys with blocks swapped with their neighbours.  Each swap is a
+    drop that no single removal repairs; short blocks (3 keys) are still
+    peeled off by the outlier split's rounds, long ones (40 keys) overlap
+    further than the probe's depth test and the split is not tried.
+    Whatever path follows, the result is exact."""
+    rng = np.random.default_rng(n)
+    for blk, paths in ((3, ("outlier",)), (40, ("runs", "general"))):
+        a = np.arange(n, dtype=np.int64)
+        starts = np.sort(rng.choice(n // (2 * blk) - 1, size=n // (200 * blk), replace=False)) * (2 * blk)
+        for p in starts:
+            a[p:p + 2 * blk] = np.concatenate([a[p + blk:p + 2 * blk], a[p:p + blk]])
+        st = check(gpu, a.astype(np.int32))
+        assert st["path"] in paths, (blk, st)
