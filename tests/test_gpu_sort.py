@@ -361,3 +361,28 @@ def test_plain_sort_refuses_stream_capture(gpu):
     gpu.sort_keys(t, dtype="int32", stream=st)
     st.synchronize()
     assert np.array_equal(from_dev(t, a), np.sort(a))
+
+
+def test_random_sizes_sweep(gpu):
+    """Sixty seeded random sizes from 2 to 300,000 keys, each with a random
+    dtype, input kind and keys/pairs choice: bit-exact against the oracle
+    (catches size-dependent launch-shape or tail handling mistakes that the
+    fixed size list misses)."""
+    rng = np.random.default_rng(2024)
+    for case in range(60):
+        n = int(rng.integers(2, 300_001))
+        kind = inputs.TYPES[int(rng.integers(0, len(inputs.TYPES)))]
+        dt = ("int32", "float32", "uint64")[int(rng.integers(0, 3))]
+        a = inputs.int32_of_type(kind, n, 500 + case)
+        if dt == "float32":
+            a = (a.astype(np.float32) * np.float32(0.25))
+        elif dt == "uint64":
+            a = (a.astype(np.int64).astype(np.uint64) << np.uint64(20)) ^ np.uint64(0x9E3779B9)
+        if rng.random() < 0.3:
+            p = np.arange(n, dtype=np.uint32)
+            gk, gp = gpu_sort_pairs(gpu, a, p, dt)
+            wk, wp = oracle.sort_pairs(a, p)
+            assert np.array_equal(bits(gk), bits(wk)) and np.array_equal(gp, wp), (case, n, kind, dt)
+        else:
+            got = gpu_sort_keys(gpu, a, dt)
+            assert np.array_equal(bits(got), bits(oracle.sort_keys(a))), (case, n, kind, dt)
