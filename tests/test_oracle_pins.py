@@ -239,6 +239,7 @@ MUTATIONS = {
     "uint64_signed": ("    uint64_t x, y;\n    memcpy(&x, a, 8);", "    int64_t x, y;\n    memcpy(&x, a, 8);"),
     "tail_dropped": ("    while (j < hi) {\n        memcpy(tmp + k * rs, a + j * rs, rs);",
                      "    while (0) {\n        memcpy(tmp + k * rs, a + j * rs, rs);"),
+    "split_off_by_one": ("    msort(r, a, tmp, mid, hi);", "    msort(r, a, tmp, mid + 1, hi);"),
 }
 
 
@@ -346,3 +347,149 @@ def test_list_sort_pins():
 def test_list_pins_catch_planted_mistakes(tmp_path):
     for name in LIST_MUTATIONS:
         assert not _lists_pins_pass(_mutant_lists(tmp_path, name)), f"mutation {name} not caught"
+
+
+# ------------- P6 ascents and Inv on tied keys; segmented payloads (Sec. 2)
+
+def _bubble_swaps(seq):
+    """Adjacent exchanges a bubble sort makes, swapping only strictly greater
+    left neighbours.  Each such exchange removes exactly one inversion and
+    the sort ends with none, so the count equals Inv (an algorithm of its
+    own, not the pair-counting definition)."""
+    a = list(seq)
+    swaps = 0
+    for end in range(len(a) - 1, 0, -1):
+        for i in range(end):
+            if a[i] > a[i + 1]:
+                a[i], a[i + 1] = a[i + 1], a[i]
+                swaps += 1
+    return swaps
+
+
+def _measure_pins_pass(run, ascents, inv):
+    """Closed forms of Sec. 2 plus the identity descents + ascents + equal
+    neighbours = n - 1, on inputs with ties."""
+    for n in (0, 1, 2, 9, 300):
+        up = np.arange(n, dtype=np.int32)
+        if ascents(up) != max(n - 1, 0) or ascents(up[::-1].copy()) != 0:
+            return False
+        eq = np.full(n, 7, dtype=np.int32)
+        if ascents(eq) != 0 or inv(eq) != 0 or run(eq) != (1 if n else 0):
+            return False
+    # k copies of 1..q: no inversion inside a copy, q(q-1)/2 between any two
+    # copies (equal values are no inversion)
+    for k, q in ((1, 5), (2, 1), (2, 6), (3, 4), (5, 7)):
+        a = np.tile(np.arange(1, q + 1, dtype=np.int32), k)
+        if inv(a) != k * (k - 1) // 2 * q * (q - 1) // 2:
+            return False
+        if ascents(a) != k * (q - 1):
+            return False
+    # Sec. 3 worked example: 16 distinct keys, Run = 12, so 15 - 11 = 4 ascents
+    g = _golden("worked_example.txt")
+    ex = np.array([int(x) for x in g["input"]], dtype=np.int32)
+    if ascents(ex) != int(g["ascents"][0]) or inv(ex) != _bubble_swaps(ex.tolist()):
+        return False
+    for dt, vals in (("int32", I32_ORDER[:3]), ("uint64", U64_ORDER[5:8]),
+                     ("float32", F32_TOTAL_ORDER[4:7].view(np.float32))):
+        for n in range(0, 8):
+            for seq in itertools.product(range(3), repeat=n):
+                a = vals[list(seq)] if n else vals[:0]
+                eqn = sum(1 for i in range(n - 1) if seq[i] == seq[i + 1])
+                d = (run(a) - 1) if n else 0
+                if d + ascents(a) + eqn != max(n - 1, 0):
+                    return False
+                if inv(a) != _bubble_swaps(seq):
+                    return False
+    return True
+
+
+def test_measures_on_tied_keys():
+    assert _measure_pins_pass(oracle.run, oracle.ascents, oracle.inv)
+
+
+def _segmented_pairs_pass(sort_segmented):
+    """Per segment, the payload order is Python's sorted() by (key, index)."""
+    rng = np.random.default_rng(44)
+    for trial in range(6):
+        lens = rng.integers(0, 40, 9)
+        lens[trial % 9] = 0
+        off = np.zeros(lens.size + 1, dtype=np.int64)
+        off[1:] = np.cumsum(lens)
+        n = int(off[-1])
+        keys = rng.integers(0, 4, n).astype(np.int32)
+        pay = np.arange(n, dtype=np.uint32)[::-1].copy()
+        ok, op = sort_segmented(keys, off, pay)
+        for s in range(lens.size):
+            a, b = int(off[s]), int(off[s + 1])
+            order = sorted(range(a, b), key=lambda i: (int(keys[i]), i))
+            if list(op[a:b]) != [int(pay[i]) for i in order]:
+                return False
+            if list(ok[a:b]) != [int(keys[i]) for i in order]:
+                return False
+    return True
+
+
+def test_segmented_pairs_match_python_definition():
+    assert _segmented_pairs_pass(oracle.sort_segmented)
+
+
+MEASURE_MUTATIONS = {
+    "ascents_count_ties": ("        if (less(a + i * ks, a + (i + 1) * ks))\n            u++;",
+                           "        if (!less(a + (i + 1) * ks, a + i * ks))\n            u++;"),
+    "inv_counts_ties": ("            if (less(a + j * ks, a + i * ks))\n                c++;",
+                        "            if (!less(a + i * ks, a + j * ks))\n                c++;"),
+    "inv_neighbours_only": ("        for (size_t j = i + 1; j < n; j++)\n            if (less(a + j * ks, a + i * ks))",
+                            "        for (size_t j = i + 1; j < n && j < i + 2; j++)\n"
+                            "            if (less(a + j * ks, a + i * ks))"),
+}
+SEGMENT_MUTATIONS = {
+    "segment_payload_not_offset": ("sort_records(dtype, k, payload + a,", "sort_records(dtype, k, payload,"),
+    "segment_payload_off_by_one": ("sort_records(dtype, k, payload + a,", "sort_records(dtype, k, payload + a + 1,"),
+}
+
+
+def _mutant_lib(tmp_path, name, old, new):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "sortrace_oracle.c")).read()
+    assert old in src, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", str(path), "-o", str(so)])
+    lib = ctypes.CDLL(str(so))
+    for fn in ("oracle_run", "oracle_ascents", "oracle_inv"):
+        getattr(lib, fn).argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
+        getattr(lib, fn).restype = ctypes.c_int64
+    lib.oracle_sort_segmented.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t]
+    return lib
+
+
+def _measure(lib, fn):
+    def f(a):
+        a = np.ascontiguousarray(a)
+        return int(getattr(lib, fn)(oracle.DTYPES[a.dtype.name], a.ctypes.data, a.size))
+    return f
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc needed")
+def test_measure_pins_catch_planted_mistakes(tmp_path):
+    for name, (old, new) in MEASURE_MUTATIONS.items():
+        lib = _mutant_lib(tmp_path, name, old, new)
+        ok = _measure_pins_pass(_measure(lib, "oracle_run"), _measure(lib, "oracle_ascents"),
+                                _measure(lib, "oracle_inv"))
+        assert not ok, f"mutation {name} not caught"
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc needed")
+def test_segmented_pins_catch_planted_mistakes(tmp_path):
+    for name, (old, new) in SEGMENT_MUTATIONS.items():
+        lib = _mutant_lib(tmp_path, name, old, new)
+
+        def sort_segmented(keys, off, pay, lib=lib):
+            k, p = keys.copy(), pay.copy()
+            # the payload-off-by-one mutant reads one past the array: give it room
+            buf = np.zeros(p.size + 1, dtype=np.uint32)
+            buf[:p.size] = p
+            lib.oracle_sort_segmented(0, k.ctypes.data, buf.ctypes.data, off.ctypes.data, off.size - 1)
+            return k, buf[:p.size]
+        assert not _segmented_pairs_pass(sort_segmented), f"mutation {name} not caught"
