@@ -1,9 +1,10 @@
 """GPU parity at the full 256M-key size of the benchmark, in the launch
 configuration bench.py times (one sr_sort_keys call on a resident array).
 
-The oracle cannot sort 2^28 keys within a test's time budget, so the checks
-are properties that hold at any size and closed forms:
-  random        the output is nondecreasing; it is a permutation of the input
+  random        element by element against the oracle's mergesort of the
+                same 2^28 keys (run in a worker thread while the GPU works);
+                as extra checks, properties that hold at any size: the
+                output is nondecreasing; it is a permutation of the input
                 (equal counts of every 16-bit prefix, equal sums of keys and
                 of squared keys); and at 64 sampled output positions p the
                 value v = out[p] has exactly the definition's rank: fewer
@@ -12,10 +13,13 @@ are properties that hold at any size and closed forms:
   reversed, nearly sorted   exactly 0 .. n-1
   few unique    exactly the input's values in order, each repeated its count
 """
+import concurrent.futures as cf
+
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1609_04471_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -31,8 +35,12 @@ def sort_on_gpu(gpu, a: np.ndarray) -> torch.Tensor:
     return t
 
 
+@pytest.mark.timeout(900)
 def test_random_256M(gpu):
     a = inputs.int32_of_type("random", N, inputs.seed_for(2, 0, N))
+    ex = cf.ThreadPoolExecutor(1)
+    want = ex.submit(oracle.sort_keys, a)
+    print("[full-size] 256M random: oracle started", flush=True)
     src = torch.from_numpy(a).to(DEV)
     out = src.clone()
     gpu.sort_keys(out, dtype="int32")
@@ -51,6 +59,12 @@ def test_random_256M(gpu):
         below = int((src < v).sum())
         at_most = int((src <= v).sum())
         assert below <= p < at_most, (p, v, below, at_most)
+    got = out.cpu().numpy()
+    del out, src, s_in, s_out
+    print("[full-size] 256M random: GPU checks done, waiting for the oracle", flush=True)
+    w = want.result()
+    ex.shutdown()
+    assert np.array_equal(got, w)
 
 
 @pytest.mark.parametrize("kind", ["reversed", "nearly"])
