@@ -173,6 +173,25 @@ sr_status sr_reserve(sr_dtype dt, size_t n, size_t nseg, void *stream);
  */
 sr_status sr_set_workspace(void *buf, size_t bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code recorded into a
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sr_sort_keys with no allocation.  Same arguments, order and result as
+ * sr_sort_keys, but its whole workspace (control block, look-back space and
+ * the merge passes' partner array) is one fixed array of 36 MiB per device
+ * that the library's code object holds until the process ends, so no call
+ * allocates or frees anything.  Limit: n x element size <= 32 MiB (8,388,608
+ * int32 or float32 keys, 4,194,304 uint64 keys); a larger n returns
+ * SR_ERR_INVALID_ARGUMENT before anything is enqueued.  The first call on a
+ * device initialises that device's array on `stream` and waits for it (one
+ * synchronization, ever).  Every call on a device shares its one array, which
+ * keeps the last call's contents: calls whose work overlaps on one device --
+ * on different streams, or from different host threads, without ordering
+ * between them -- race and give wrong results; order them on one stream.
+ * sr_last_stats does not report these calls.  Errors as sr_sort_keys.
+ */
+sr_status sr_sort_keys_noalloc(sr_dtype dt, void *keys, size_t n, void *stream);
+
 /* Frees the workspace the library holds for `stream` on the current device
  * (after synchronizing it; a buffer set by sr_set_workspace is the caller's
  * and is not freed).  Call before destroying a stream that sorted. */

@@ -2528,6 +2528,20 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
         p[i] = 0;
 }
 
+// The path-forcing option lives in the control block: rewrite it when the
+// option changed since this workspace last saw it.
+void apply_force(Workspace* ws, hipStream_t st) {
+    int force;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        force = g_force_path;
+    }
+    if (ws->force != force) {
+        hipLaunchKernelGGL(k_set_force, dim3(1), dim3(1), 0, st, ws->ctl, force);
+        ws->force = force;
+    }
+}
+
 // Workspace of at least `data_bytes` scratch bytes and `aux_bytes` of
 // zero-initialised look-back space for (device, stream).
 sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size_t aux_bytes = 0) {
@@ -2598,15 +2612,7 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "zero");
     }
-    int force;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        force = g_force_path;
-    }
-    if (ws->force != force) {
-        hipLaunchKernelGGL(k_set_force, dim3(1), dim3(1), 0, st, ws->ctl, force);
-        ws->force = force;
-    }
+    apply_force(ws, st);
     *out = ws;
     return SR_OK;
 }
@@ -2626,6 +2632,68 @@ size_t aux_bound(int64_t n) {
 void* ws_data(Workspace* ws) { return ws->base; }
 unsigned long long* ws_slots(Workspace* ws) {
     return reinterpret_cast<unsigned long long*>((char*)ws->hdr + kCtlBytes);
+}
+
+// ------------------------------------------------ allocation-free sorts
+// sr_sort_keys_noalloc keeps its whole workspace (header, look-back space,
+// data scratch) in one array per device that lives in the code object, so a
+// call never allocates device memory.  The array's name is a host-side
+// stand-in in host code: its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is passed to kernels.
+constexpr size_t kNoAllocKeyBytes = (size_t)32 << 20;  // largest n x key size
+constexpr int64_t kNoAllocMaxN32 = (int64_t)(kNoAllocKeyBytes / 4);
+constexpr size_t kNoAllocBytes = (size_t)36 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+    bool ready = false;
+    Workspace ws;  // views of the array; never grown or freed
+};
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+std::mutex g_noalloc_mu;
+
+// The device's allocation-free workspace; the first call on a device looks up
+// the array's address, zeroes its header and look-back space on `st` and
+// waits for that, so every later call (on any stream) finds it initialised.
+sr_status noalloc_workspace(hipStream_t st, Workspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(SR_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoAllocDevice& d = g_noalloc[dev];
+    if (!d.ready) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return fail(SR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        const size_t aux = round_up(aux_bound(kNoAllocMaxN32), 4096);
+        if (kHdrBytes + aux + kNoAllocKeyBytes + ((size_t)1 << 20) > kNoAllocBytes)
+            return fail(SR_ERR_INTERNAL, "allocation-free scratch layout does not fit its array");
+        char* p = static_cast<char*>(ptr);
+        Workspace& w = d.ws;
+        w.hdr = p;
+        w.ctl = reinterpret_cast<Ctl*>(p);
+        w.aux = p + kHdrBytes;
+        w.aux_bytes = aux;
+        w.base = p + kHdrBytes + aux;
+        w.bytes = kNoAllocBytes - kHdrBytes - aux;
+        w.external = true;
+        hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, st, (unsigned long long*)p,
+                           (int64_t)((kHdrBytes + aux) / 8));
+        hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, st, w.ctl);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "allocation-free scratch initialisation");
+        w.force = -1;
+        d.ready = true;
+    }
+    apply_force(&d.ws, st);
+    *out = &d.ws;
+    return SR_OK;
 }
 
 // Resident workgroups of a kernel on the whole device (persistent grids).
@@ -2663,9 +2731,11 @@ int ceil_log2(int64_t x) {
 
 // st: the caller's stream (workspace and statistics are kept per stream);
 // ls: the stream the kernels are launched on (st, or a capture stream).
+// noalloc: take the device's allocation-free workspace instead of the
+// stream's (nothing is allocated; the call's statistics are not recorded).
 template <class C, bool PAIRS>
 sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool prepare_only = false,
-                    hipStream_t ls = nullptr) {
+                    hipStream_t ls = nullptr, bool noalloc = false) {
     if (ls == nullptr) ls = st;
     {
         // a plain sort recorded into the caller's stream capture would be
@@ -2696,6 +2766,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3(1), dim3(TN::TWG), 0, ls, keys, keys,
                            pay, pay, n, 0, (const Ctl*)nullptr, (const RunTile*)nullptr);
         SR_LAUNCH_CHECK("tile_sort");
+        if (noalloc) return SR_OK;
         lc.trivial = 1;
         std::lock_guard<std::mutex> lk(g_mu);
         g_last[st] = lc;
@@ -2720,8 +2791,16 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     // run descriptors and the run plan
     const size_t rdesc_bytes = runs_ok ? round_up((size_t)ncls * sizeof(RunTile), 256) : 0;
     const size_t rarea_bytes = runs_ok ? round_up(sizeof(RunArea), 256) : 0;
-    sr_status s = get_workspace(st, co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0), &ws,
-                                4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes);
+    const size_t data_need = co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0);
+    const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes;
+    sr_status s;
+    if (noalloc) {
+        s = noalloc_workspace(st, &ws);
+        if (s == SR_OK && (data_need > ws->bytes || aux_need > ws->aux_bytes))
+            s = fail(SR_ERR_INTERNAL, "allocation-free scratch smaller than the call needs");
+    } else {
+        s = get_workspace(st, data_need, &ws, aux_need);
+    }
     if (s != SR_OK || prepare_only) return s;
     Ctl* ctl = ws->ctl;
     char* wd = static_cast<char*>(ws_data(ws));
@@ -2848,6 +2927,7 @@ tile_done:
             SR_LAUNCH_CHECK("merge");
         }
     }
+    if (noalloc) return SR_OK;
     lc.trivial = 0;
     lc.ctl = ctl;
     lc.tile = T;
@@ -3088,6 +3168,24 @@ sr_status sr_sort_keys(sr_dtype dt, void* keys, size_t n, void* stream) {
     case SR_INT32: return sort_dispatch<CodecI32, false>(dt, keys, nullptr, (int64_t)n, st);
     case SR_FLOAT32: return sort_dispatch<CodecF32, false>(dt, keys, nullptr, (int64_t)n, st);
     case SR_UINT64: return sort_dispatch<CodecU64, false>(dt, keys, nullptr, (int64_t)n, st);
+    }
+    return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
+}
+
+sr_status sr_sort_keys_noalloc(sr_dtype dt, void* keys, size_t n, void* stream) {
+    g_err.clear();
+    sr_status s = check_keys(dt, keys, n);
+    if (s != SR_OK) return s;
+    if (n * (size_t)elem_bytes(dt) > kNoAllocKeyBytes)
+        return fail(SR_ERR_INVALID_ARGUMENT, "sr_sort_keys_noalloc: " + std::to_string(n) + " keys of " +
+                                                 std::to_string(elem_bytes(dt)) + " bytes exceed its limit of " +
+                                                 std::to_string(kNoAllocKeyBytes) + " bytes of keys");
+    if (n <= 1) return SR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    switch (dt) {
+    case SR_INT32: return sort_impl<CodecI32, false>(keys, nullptr, (int64_t)n, st, false, nullptr, true);
+    case SR_FLOAT32: return sort_impl<CodecF32, false>(keys, nullptr, (int64_t)n, st, false, nullptr, true);
+    case SR_UINT64: return sort_impl<CodecU64, false>(keys, nullptr, (int64_t)n, st, false, nullptr, true);
     }
     return fail(SR_ERR_INVALID_ARGUMENT, "unknown dtype");
 }

@@ -33,7 +33,7 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
            "sr_last_error_message", "sr_set_option", "sr_profile_collect", "sr_copy_bandwidth_probe",
            "sr_server_create", "sr_server_submit", "sr_server_now", "sr_server_wait_idle",
            "sr_server_records", "sr_server_destroy", "sr_tune_set", "sr_tune_get",
-           "sr_measure_presortedness", "sr_sort_lists", "sr_set_workspace")
+           "sr_measure_presortedness", "sr_sort_lists", "sr_set_workspace", "sr_sort_keys_noalloc")
 SR_MEASURE_INV = 1
 
 # Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64
     lib.sr_sort_keys.argtypes = [i32, vp, sz, vp]
+    lib.sr_sort_keys_noalloc.argtypes = [i32, vp, sz, vp]
     lib.sr_sort_pairs.argtypes = [i32, vp, vp, sz, vp]
     lib.sr_sort_segmented.argtypes = [i32, vp, vp, sz, vp, sz, vp]
     lib.sr_measure.argtypes = [i32, vp, sz, ctypes.POINTER(ctypes.c_int64), vp]
@@ -177,6 +178,17 @@ def sort_keys(keys, dtype: str | None = None, stream=None):
     lib = load()
     dt = _key_dtype(keys, dtype)
     _check(lib.sr_sort_keys(dt, _dev(keys, "keys"), keys.numel(), _stream(stream)), "sr_sort_keys")
+    return keys
+
+
+def sort_keys_noalloc(keys, dtype: str | None = None, stream=None):
+    """sort_keys through the allocation-free entry point (one fixed scratch
+    array per device, shared by every call: order overlapping calls on one
+    stream).  Returns keys."""
+    lib = load()
+    dt = _key_dtype(keys, dtype)
+    _check(lib.sr_sort_keys_noalloc(dt, _dev(keys, "keys"), keys.numel(), _stream(stream)),
+           "sr_sort_keys_noalloc")
     return keys
 
 
