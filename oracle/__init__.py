@@ -33,7 +33,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared",
-                               "-fPIC", _SRC, "-o", tmp])
+                               "-fPIC", _SRC, "-o", tmp, "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -55,6 +55,8 @@ def _load():
         lib.oracle_sort_segmented.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_size_t]
         lib.oracle_sort_segmented.restype = c_int
         lib.oracle_sort_lists.argtypes = [c_void_p, c_size_t, c_size_t]
+        lib.oracle_sort_keys_parallel.argtypes = [c_int, c_void_p, c_size_t, c_int]
+        lib.oracle_sort_keys_parallel.restype = c_int
         lib.oracle_sort_lists.restype = c_int
         for name in ("oracle_run", "oracle_ascents", "oracle_inv", "oracle_mono"):
             getattr(lib, name).argtypes = [c_int, c_void_p, c_size_t]
@@ -83,6 +85,15 @@ def sort_keys(keys: np.ndarray) -> np.ndarray:
     """Stable top-down mergesort of keys (the unique sorted permutation)."""
     out = np.ascontiguousarray(keys).copy()
     _check(_load().oracle_sort_keys(_dt(out), _ptr(out), out.size), "sort_keys")
+    return out
+
+
+def sort_keys_parallel(keys: np.ndarray, threads: int) -> np.ndarray:
+    """The same mergesort on `threads` host threads (a power of two is used);
+    for timing a CPU baseline only -- tests compare it with sort_keys."""
+    out = np.ascontiguousarray(keys).copy()
+    _check(_load().oracle_sort_keys_parallel(_dt(out), _ptr(out), out.size, int(threads)),
+           "sort_keys_parallel")
     return out
 
 

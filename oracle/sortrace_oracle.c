@@ -46,10 +46,18 @@
  *                                          (lexicographic), same mergesort
  *   oracle_run / oracle_inv / oracle_mono  presortedness measures of Sec. 2
  *                                          (Run, Inv, Mono)
+ *   oracle_sort_keys_parallel              the same mergesort on several host
+ *                                          threads (chunks sorted in parallel,
+ *                                          then each merge round's merges cut
+ *                                          into equal parts by Merge Path
+ *                                          co-ranks); used only to time a CPU
+ *                                          baseline on all host cores, and
+ *                                          checked against oracle_sort_keys
  *
  * Every pointer is host memory owned by the caller.  Return value 0 = OK,
  * -1 = bad argument.  Build: gcc -O2 -shared -fPIC.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -255,6 +263,128 @@ int oracle_sort_segmented(int dtype, void *keys, uint32_t *payload,
         if (rc != 0)
             return rc;
     }
+    return 0;
+}
+
+/* ------------------------------------------- multi-threaded (timing only) */
+
+typedef struct {
+    const rec_t *r;
+    unsigned char *a, *tmp;
+    size_t lo, hi;
+} sort_part;
+
+static void *sort_part_run(void *p)
+{
+    sort_part *j = (sort_part *)p;
+    msort(j->r, j->a, j->tmp, j->lo, j->hi);
+    return NULL;
+}
+
+/* Of the first d records of the stable merge of a[alo, ahi) and a[blo, bhi),
+ * how many come from the first run (ties go to the first run). */
+static size_t co_rank(const rec_t *r, const unsigned char *a, size_t alo, size_t ahi,
+                      size_t blo, size_t bhi, size_t d)
+{
+    size_t na = ahi - alo, nb = bhi - blo, rs = r->rs;
+    size_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+    while (lo < hi) {
+        size_t mid = lo + (hi - lo) / 2;
+        /* a[alo + mid] is among the first d unless b[blo + d - 1 - mid] precedes it */
+        if (!r->less(a + (blo + d - 1 - mid) * rs, a + (alo + mid) * rs))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+typedef struct {
+    const rec_t *r;
+    const unsigned char *src;
+    unsigned char *dst;
+    size_t alo, ahi, blo, bhi, out;
+} merge_part;
+
+static void *merge_part_run(void *p)
+{
+    merge_part *j = (merge_part *)p;
+    size_t i = j->alo, k = j->blo, o = j->out, rs = j->r->rs;
+    while (i < j->ahi && k < j->bhi) {
+        if (j->r->less(j->src + k * rs, j->src + i * rs)) {
+            memcpy(j->dst + o * rs, j->src + k * rs, rs);
+            k++;
+        } else {
+            memcpy(j->dst + o * rs, j->src + i * rs, rs);
+            i++;
+        }
+        o++;
+    }
+    memcpy(j->dst + o * rs, j->src + i * rs, (j->ahi - i) * rs);
+    o += j->ahi - i;
+    memcpy(j->dst + o * rs, j->src + k * rs, (j->bhi - k) * rs);
+    return NULL;
+}
+
+/* Keys only, on up to `threads` host threads (rounded down to a power of
+ * two, at most 256).  The result is the same unique sorted permutation as
+ * oracle_sort_keys. */
+int oracle_sort_keys_parallel(int dtype, void *keys, size_t n, int threads)
+{
+    rec_t r;
+    if (setup(&r, dtype, 0) != 0 || threads < 1)
+        return -1;
+    if (n == 0)
+        return 0;
+    if (keys == NULL)
+        return -1;
+    int t = 1;
+    while (t * 2 <= threads && t < 256)
+        t *= 2;
+    unsigned char *a = (unsigned char *)keys; /* keys-only records are the keys */
+    unsigned char *tmp = (unsigned char *)malloc(n * r.rs);
+    size_t *b = (size_t *)malloc((size_t)(t + 1) * sizeof(size_t));
+    pthread_t *th = (pthread_t *)malloc((size_t)t * sizeof(pthread_t));
+    sort_part *sp = (sort_part *)malloc((size_t)t * sizeof(sort_part));
+    merge_part *mp = (merge_part *)malloc((size_t)t * sizeof(merge_part));
+    if (!tmp || !b || !th || !sp || !mp) {
+        free(tmp); free(b); free(th); free(sp); free(mp);
+        return -1;
+    }
+    for (int i = 0; i <= t; i++)
+        b[i] = n / (size_t)t * (size_t)i + (n % (size_t)t) * (size_t)i / (size_t)t;
+    for (int i = 0; i < t; i++) {
+        sp[i] = (sort_part){&r, a, tmp, b[i], b[i + 1]};
+        pthread_create(&th[i], NULL, sort_part_run, &sp[i]);
+    }
+    for (int i = 0; i < t; i++)
+        pthread_join(th[i], NULL);
+    unsigned char *src = a, *dst = tmp;
+    for (int runs = t; runs > 1; runs /= 2) {
+        int per = t / (runs / 2); /* threads per merge */
+        for (int g = 0; g < runs / 2; g++) {
+            size_t alo = b[2 * g], mid = b[2 * g + 1], bhi = b[2 * g + 2], len = bhi - alo;
+            for (int q = 0; q < per; q++) {
+                size_t d0 = len * (size_t)q / (size_t)per, d1 = len * (size_t)(q + 1) / (size_t)per;
+                size_t i0 = co_rank(&r, src, alo, mid, mid, bhi, d0);
+                size_t i1 = co_rank(&r, src, alo, mid, mid, bhi, d1);
+                mp[g * per + q] = (merge_part){&r, src, dst, alo + i0, alo + i1,
+                                               mid + (d0 - i0), mid + (d1 - i1), alo + d0};
+            }
+        }
+        for (int i = 0; i < t; i++)
+            pthread_create(&th[i], NULL, merge_part_run, &mp[i]);
+        for (int i = 0; i < t; i++)
+            pthread_join(th[i], NULL);
+        for (int g = 0; g <= runs / 2; g++)
+            b[g] = b[2 * g];
+        unsigned char *x = src;
+        src = dst;
+        dst = x;
+    }
+    if (src != a)
+        memcpy(a, src, n * r.rs);
+    free(tmp); free(b); free(th); free(sp); free(mp);
     return 0;
 }
 

@@ -493,3 +493,20 @@ def test_segmented_pins_catch_planted_mistakes(tmp_path):
             lib.oracle_sort_segmented(0, k.ctypes.data, buf.ctypes.data, off.ctypes.data, off.size - 1)
             return k, buf[:p.size]
         assert not _segmented_pairs_pass(sort_segmented), f"mutation {name} not caught"
+
+
+# ----------------- the multi-threaded variant used to time a CPU baseline
+
+@pytest.mark.parametrize("dtype", ["int32", "uint64", "float32"])
+def test_parallel_variant_equals_the_oracle(dtype):
+    for n in (0, 1, 2, 3, 7, 100, 1001, 65537):
+        for threads in (1, 2, 3, 8, 16):
+            if dtype == "int32":
+                a = inputs.random_int32(n, n + threads)
+                a[::3] = 5
+            elif dtype == "uint64":
+                a = inputs.stream(n, n)
+            else:
+                a = inputs.normal_float32(n, seed=n + 1)
+            got = oracle.sort_keys_parallel(a, threads)
+            assert np.array_equal(bits(got), bits(oracle.sort_keys(a))), (n, threads)
