@@ -66,10 +66,19 @@ typedef enum {
                               place, disordered tiles sorted, runs whose values are
                               already in order joined, then a merge tree over the
                               remaining leaves (Sec. 3 natural runs, Sec. 2 Mono) */
-    SR_PATH_FEW = 5        /* few distinct keys (keys only): equal buckets around at
+    SR_PATH_FEW = 5,       /* few distinct keys (keys only): equal buckets around at
                               most 64 sampled values -- the GPU form of 3-way
                               partitioning (Sec. 4, k-limited of Sec. 2); keys
                               between the sampled values are sorted separately */
+    SR_PATH_NEAR = 6       /* tile sort, then two rounds of neighbour merges: tile
+                              pairs (0,1),(2,3),... and then (1,2),(3,4),...; taken
+                              when the sorted tiles show that every tile overlaps
+                              only its neighbours, by at most half a tile (keys
+                              displaced by less than half a tile: the k-distance
+                              class of Sec. 2, Table 1's nearly sorted type); keys
+                              and pairs.  Reported on the general plan's launches:
+                              a sort that is not NEAR-shaped takes the full merge
+                              tree instead */
 } sr_path;
 
 typedef struct {
@@ -209,7 +218,12 @@ sr_status sr_release_stream(void *stream);
  * sr_sort_batch (sr_sort_keys for a batch of one).  Batches on different
  * streams overlap on the device.  streams = 1 with max_batch_requests = 1 is
  * the plain one-at-a-time FIFO server.  Every result is what sr_sort_keys
- * gives for the same array alone.
+ * gives for the same array alone.  Scratch: sr_server_create reserves, on
+ * every stream, the workspace of a batch of max_batch_keys keys of each
+ * dtype (int32, float32, uint64), so the worker never allocates; the
+ * footprint charged per request (2 x n x element bytes) is the admission
+ * rule's bookkeeping of the keys plus the share of that reserved scratch its
+ * sort uses.
  */
 typedef struct sr_server sr_server;
 
@@ -231,9 +245,14 @@ typedef struct {
 } sr_request_record;
 
 sr_status sr_server_create(const sr_server_config *cfg, sr_server **out);
-/* Errors: a request whose footprint exceeds the budget or max_batch_keys, or
- * an arrival earlier than the previous submission's. */
-sr_status sr_server_submit(sr_server *s, sr_dtype dt, void *keys, size_t n, uint64_t tag, double t_arrive);
+/* ready_event: NULL, or a hipEvent_t recorded on the producer's stream after
+ * the keys were written; the batch's stream waits for it before the sort, so
+ * keys produced asynchronously are never sorted early.  The event must stay
+ * valid until the request is reported finished.  Errors: a request whose
+ * footprint exceeds the budget or max_batch_keys, or an arrival earlier than
+ * the previous submission's. */
+sr_status sr_server_submit(sr_server *s, sr_dtype dt, void *keys, size_t n, uint64_t tag, double t_arrive,
+                           void *ready_event);
 double sr_server_now(sr_server *s);
 /* Waits until every submitted request has finished (SR_ERR_INTERNAL on timeout). */
 sr_status sr_server_wait_idle(sr_server *s, double timeout_s);
@@ -297,7 +316,8 @@ const char *sr_last_error_message(void);
  * Options (process-wide).  Names:
  *   "force_path"  -1 = let the device plan decide (default); otherwise an
  *                 sr_path value the plan is forced to when it is safe
- *                 (SR_PATH_GENERAL is always safe).
+ *                 (SR_PATH_GENERAL is always safe; forcing it also rules out
+                 SR_PATH_NEAR, so the full merge tree runs).
  *   "profile"     1 = record a HIP event pair around every kernel the sort
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
@@ -305,6 +325,8 @@ const char *sr_last_error_message(void);
  *   "few_path"    1 = keys-only sorts may take SR_PATH_FEW (default); 0 = never.
  *                 A forced SR_PATH_FEW still falls back to SR_PATH_GENERAL when
  *                 more than a quarter of the keys miss the sampled values.
+ *   "near_path"   1 = general sorts may finish as SR_PATH_NEAR when their
+ *                 sorted tiles allow it (default); 0 = never.
  *   "runs_path"   1 = keys-only and pairs sorts may take SR_PATH_RUNS
  *                 (default); 0 = never.
  *                 A forced SR_PATH_RUNS still falls back to SR_PATH_GENERAL
@@ -315,8 +337,17 @@ const char *sr_last_error_message(void);
  *                 options) combination is seen, and replays it afterwards
  *                 with one hipGraphLaunch (the segment plan is recomputed on
  *                 the device, so new data and new offsets in the same buffers
- *                 are handled); 0 = plain launches (default).  sr_sort_keys /
- *                 sr_sort_pairs always launch directly.
+ *                 are handled); 0 = plain launches (default).
+ *   "graph_plain" 1 = with "graph" on, sr_sort_keys / sr_sort_pairs use the
+ *                 same capture-and-replay cache; 0 = they launch directly
+ *                 (default).
+ * Recording into the caller's own stream capture: sr_sort_keys,
+ * sr_sort_pairs and sr_sort_keys_noalloc may be called on a capturing stream
+ * when they need no allocation there -- the stream's workspace already holds
+ * the size (sr_reserve, sr_set_workspace, or an earlier sort of that size on
+ * the stream; for sr_sort_keys_noalloc, an earlier call on the device) --
+ * else they return SR_ERR_UNSUPPORTED and record nothing.  Each replay sorts
+ * the buffers as they are at replay time.
  * The four launch-shape options below default to "auto": the matching row
  * of the tuning table (sr_tune_set) decides, else the built-in rule given
  * with each.  A value set here overrides the table for every sort.
@@ -356,16 +387,21 @@ typedef struct {
     int32_t merge_items;   /* 8 or 16; 0 = unset */
     int32_t partition;     /* 1 = separate partition launch, 0 = fused search; -1 = unset */
     int32_t nontemporal;   /* 1 or 0; -1 = unset */
+    int32_t segmented;     /* 0 = plain sorts; 1 = sr_sort_segmented / sr_sort_batch, whose
+                              rows are looked up by the total key count and use only
+                              tile_variant and merge_items (32-bit keys, keys only;
+                              partition and nontemporal must be unset there) */
+    int32_t pad;           /* 0 */
 } sr_tune_entry;
 
 /* Replaces the process-wide tuning table with `count` rows copied from host
  * memory (count 0 clears it; entries may then be NULL).  Rows are validated
  * first: a bad dtype, a negative min_n, a field outside its values, or two
- * rows with the same (dtype, pairs, min_n) return SR_ERR_INVALID_ARGUMENT and
+ * rows with the same (dtype, pairs, segmented, min_n) return SR_ERR_INVALID_ARGUMENT and
  * leave the table unchanged.  At most 1024 rows. */
 sr_status sr_tune_set(const sr_tune_entry *entries, int64_t count);
 
-/* Copies up to `cap` rows of the table (sorted by dtype, pairs, min_n) to
+/* Copies up to `cap` rows of the table (sorted by dtype, pairs, segmented, min_n) to
  * host memory and stores the row count in *count. */
 sr_status sr_tune_get(sr_tune_entry *out, int64_t cap, int64_t *count);
 

@@ -12,6 +12,11 @@ the previous band's choice, so that timing noise does not flip rows):
   tile_variant  32-bit keys: 512 x 16 or 1024 x 8 threads x keys per tile;
   merge_items   32-bit keys, fused merge: 8 or 16 outputs per thread.
 
+Segmented and batched sorts (rows with "segmented": true, looked up by the
+total key count) are swept separately on the batched workload's mix --
+log-uniform segment lengths in [16, 262144] -- over tile_variant and
+merge_items (32-bit keys, keys only).
+
 The merge fan-in is 2 on every path (one pass halves the sorted pieces), so
 it is not a swept field.  Inputs are uniform random keys of the band's size
 (the case that runs every merge pass), generated on the device from a fixed
@@ -78,7 +83,8 @@ def compress(rows: list) -> list:
     out = []
     for r in rows:
         p = out[-1] if out else None
-        if p and (p["dtype"], p["pairs"]) == (r["dtype"], r["pairs"]) and \
+        if p and (p["dtype"], p["pairs"], p.get("segmented", False)) == \
+                (r["dtype"], r["pairs"], r.get("segmented", False)) and \
                 all(p.get(f) == r.get(f) for f in TUNE_FIELDS):
             continue
         out.append(r)
@@ -94,8 +100,8 @@ def validate(table: dict) -> list:
     for r in table["rows"]:
         if r["dtype"] not in DTYPES:
             raise ValueError(f"bad dtype {r['dtype']!r}")
-        rows.append({"dtype": r["dtype"], "pairs": bool(r["pairs"]), "min_n": int(r["min_n"]),
-                     **{f: int(r[f]) for f in TUNE_FIELDS if f in r}})
+        rows.append({"dtype": r["dtype"], "pairs": bool(r["pairs"]), "segmented": bool(r.get("segmented", False)),
+                     "min_n": int(r["min_n"]), **{f: int(r[f]) for f in TUNE_FIELDS if f in r}})
     return rows
 
 
@@ -210,6 +216,97 @@ def sweep(dtypes=("int32", "uint64", "float32"), kinds=(False, True), lo=16, hi=
             "reps": reps, "seed": seed, "margin": margin, "rows": rows}
 
 
+def seg_candidates(dtype: str) -> list:
+    """Launch shapes of segmented / batched sorts: 32-bit keys only."""
+    if KEY_BYTES[dtype] != 4:
+        return []
+    return [{"tile_variant": t, "merge_items": m} for t in (0, 1) for m in (8, 16)]
+
+
+def _segment_offsets(total: int, seed: int, lo: int = 16, hi: int = 262144):
+    """CSR offsets of log-uniform segment lengths in [lo, hi] (the batched-sort
+    workload's mix) summing to `total` (the last segment is cut)."""
+    import numpy as np
+    from . import inputs
+    lens, got, k = [], 0, 0
+    while got < total:
+        for L in inputs.segment_lengths(256, seed + k, lo, hi):
+            L = int(min(L, total - got))
+            lens.append(L)
+            got += L
+            if got >= total:
+                break
+        k += 1
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    return off
+
+
+def time_seg_shape(dtype: str, src, off, shape, reps: int, stream):
+    import torch
+    from . import sortrace
+    sortrace.tune_set([] if shape is None else
+                      [{"dtype": dtype, "pairs": False, "segmented": True, "min_n": 0, **shape}])
+    keys = torch.empty_like(src)
+    times = []
+    with torch.cuda.stream(stream):
+        for i in range(reps + 1):
+            keys.copy_(src)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sortrace.sort_segmented(keys, off, dtype=dtype, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            if i:
+                times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2], keys
+
+
+def sweep_segmented(dtypes=("int32", "float32"), lo=20, hi=26, step=2, reps=5, seed=4321, margin=0.02,
+                    log=print) -> list:
+    """Rows for segmented / batched sorts: per dtype and total-size band, the
+    fastest tile shape and merge outputs per thread on the log-uniform
+    segment mix, each output checked against the built-in shape's."""
+    import torch
+    from . import sortrace
+    sortrace.load()
+    for name, auto in (("tile_variant", -1), ("merge_items", 0)):
+        sortrace.set_option(name, auto)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    old = sortrace.tune_get()
+    rows = []
+    try:
+        for dtype in dtypes:
+            sizes = [1 << b for b in range(lo, hi + 1, step)]
+            for n, start in zip(sizes, band_starts(sizes)):
+                src = _random_keys(dtype, n, seed + n, dev)
+                off = torch.from_numpy(_segment_offsets(n, seed + n)).to(dev)
+                torch.cuda.synchronize()
+                builtin_ms, ref = time_seg_shape(dtype, src, off, None, reps, stream)
+                timed = []
+                for shape in seg_candidates(dtype):
+                    ms, out = time_seg_shape(dtype, src, off, shape, reps, stream)
+                    if not torch.equal(out, ref):
+                        raise RuntimeError(f"segmented {dtype} n={n} {shape}: output differs")
+                    timed.append((ms, shape))
+                    del out
+                prev = rows[-1] if rows and rows[-1]["dtype"] == dtype else None
+                best = pick(timed, prev, margin)
+                rows.append({"dtype": dtype, "pairs": False, "segmented": True, "min_n": start, **best[1],
+                             "measured_n": n, "segments": int(off.numel() - 1), "ms": round(best[0], 5),
+                             "builtin_ms": round(builtin_ms, 5)})
+                log(f"[autotune] segmented {dtype:7s} n=2^{int(math.log2(n))} ({off.numel() - 1} segments): "
+                    f"{best[1]} {best[0]:.4f} ms (built-in {builtin_ms:.4f} ms)")
+                del src, off, ref
+                torch.cuda.empty_cache()
+    finally:
+        sortrace.tune_set(old)
+    return rows
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", required=True)
@@ -222,12 +319,24 @@ def main(argv=None) -> int:
     ap.add_argument("--margin", type=float, default=0.02,
                     help="keep the previous band's shape when it is within this fraction of the best")
     ap.add_argument("--keep-all", action="store_true", help="keep rows equal to the previous one")
+    ap.add_argument("--segmented-into", default=None, metavar="TABLE",
+                    help="sweep only the segmented / batched rows (total sizes 2^20 .. 2^26) and write them "
+                         "with the plain rows of TABLE")
     a = ap.parse_args(argv)
-    kinds = tuple({"keys": False, "pairs": True}[k] for k in a.kinds.split(","))
-    table = sweep(tuple(a.dtypes.split(",")), kinds, a.lo, a.hi, a.step, a.reps, margin=a.margin,
-                  log=lambda s: print(s, flush=True))
-    if not a.keep_all:
-        table["rows"] = compress(table["rows"])
+    say = lambda s: print(s, flush=True)  # noqa: E731
+    if a.segmented_into:
+        with open(a.segmented_into) as f:
+            table = json.load(f)
+        validate(table)
+        seg = sweep_segmented(reps=a.reps, margin=a.margin, log=say)
+        table["rows"] = [r for r in table["rows"] if not r.get("segmented", False)] + \
+            (seg if a.keep_all else compress(seg))
+    else:
+        kinds = tuple({"keys": False, "pairs": True}[k] for k in a.kinds.split(","))
+        table = sweep(tuple(a.dtypes.split(",")), kinds, a.lo, a.hi, a.step, a.reps, margin=a.margin, log=say)
+        table["rows"] += sweep_segmented(reps=a.reps, margin=a.margin, log=say)
+        if not a.keep_all:
+            table["rows"] = compress(table["rows"])
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
         f.write("\n")

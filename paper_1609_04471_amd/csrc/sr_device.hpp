@@ -73,6 +73,8 @@ struct Ctl {
     int dual;                         // OUTLIER beside a run plan (the sample's turning points are rare)
     unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
     unsigned long long run[4];        // RUNS: merge leaves, merge passes, keys reversed, keys in dense pieces
+    unsigned int near_bad;            // GENERAL: some sorted tile overlaps more than its neighbours allow
+    unsigned int pad1;
 };
 
 // Plain relaxed agent-scope accessors (coherent across the XCDs' L2s), for
@@ -88,26 +90,36 @@ __device__ __forceinline__ int ld_agent(const int* p) {
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Resets of words that a later launch updates with atomics are agent-scope
+// atomic stores too: a plain store may sit dirty in one XCD's L2 and be
+// written back after the later launch's atomics, undoing their counts.
+__device__ __forceinline__ void st_agent(unsigned int* p, unsigned int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ------------------------------------------------------ cross-lane exchange
 // Value held by lane (lane ^ M) of the same wavefront.  DPP covers the masks
-// that stay inside a row of 16 lanes, ds_swizzle's bit mode the masks below
+// that stay inside a row of 16 lanes (every lane has its source inside the
+// row, so no "old" value is needed), ds_swizzle's bit mode the masks below
 // 32, ds_bpermute the rest.  All lanes must be active.
 template <int M>
 __device__ __forceinline__ uint32_t xlane(uint32_t v) {
     const int x = (int)v;
     if constexpr (M == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
     } else if constexpr (M == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
     } else if constexpr (M == 3) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, true);  // quad_perm 3,2,1,0
     } else if constexpr (M == 7) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, true); // row_half_mirror
     } else if constexpr (M == 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false); // row_ror:8
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, true); // row_ror:8
     } else if constexpr (M == 15) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); // row_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, true); // row_mirror
     } else if constexpr (M < 32) {
         // bit mode: and_mask = 0x1F, or_mask = 0, xor_mask = M
         return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x1F | (M << 10));
@@ -152,6 +164,22 @@ __device__ __forceinline__ KeyPos<U> emax(const KeyPos<U>& a, const KeyPos<U>& b
 template <int M, class U>
 __device__ __forceinline__ KeyPos<U> xlane(const KeyPos<U>& v) {
     return KeyPos<U>{xlane<M>(v.k), xlane<M>(v.p)};
+}
+
+// One side of a cross-lane compare-exchange: the lane holding x keeps the
+// larger of (x, partner) when `upper`, else the smaller.  For 32-bit keys
+// that is the median of (x, p, 0) or (x, p, ~0): one v_med3_u32 instead of a
+// min, a max and a select.
+template <class E>
+__device__ __forceinline__ E keep_side(const E& x, const E& p, bool upper) {
+    return upper ? emax(x, p) : emin(x, p);
+}
+__device__ __forceinline__ uint32_t keep_side(uint32_t x, uint32_t p, bool upper) {
+    const uint32_t bound = upper ? 0xFFFFFFFFu : 0u;
+    const uint32_t lo = x < p ? x : p;
+    const uint32_t hi = x < p ? p : x;
+    const uint32_t t = hi < bound ? hi : bound;
+    return lo < t ? t : lo;
 }
 
 template <class E>
@@ -216,7 +244,7 @@ __device__ __forceinline__ void half_cleaner_lanes(E (&v)[N], unsigned lane) {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         const E p = xlane<DL>(v[r]);
-        v[r] = upper ? emax(v[r], p) : emin(v[r], p);
+        v[r] = keep_side(v[r], p, upper);
     }
     if constexpr (DL > 1) half_cleaner_lanes<DL / 2>(v, lane);
 }
@@ -239,7 +267,7 @@ __device__ __forceinline__ void wave_merge_level(E (&v)[N], unsigned lane) {
 #pragma unroll
     for (int r = 0; r < N; ++r) p[r] = xlane<G - 1>(v[N - 1 - r]);
 #pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = upper ? emax(v[r], p[r]) : emin(v[r], p[r]);
+    for (int r = 0; r < N; ++r) v[r] = keep_side(v[r], p[r], upper);
     if constexpr (G >= 4) half_cleaner_lanes<G / 4>(v, lane);
     half_cleaners_in_registers(v);
     if constexpr (G < kWave) wave_merge_level<G * 2>(v, lane);

@@ -936,13 +936,13 @@ __device__ void few_plan(Ctl* ctl, int64_t n, FewTable* ft, int64_t T_sort) {
     const int nb = 2 * (int)ft->ns + 1;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         unsigned long long t = 0;
-        for (int c = 0; c < kFewCopies; ++c) t += ft->cnt[c][b];
+        for (int c = 0; c < kFewCopies; ++c) t += ld_agent(&ft->cnt[c][b]);
         s_tot[b] = t;
         ft->tot[b] = t;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const unsigned long long m = ctl->m;
+    const unsigned long long m = ld_agent(&ctl->m);
     long long o = 0, bp = 0;
     for (int b = 0; b < nb; ++b) {
         ft->off[b] = o;
@@ -1019,7 +1019,7 @@ __device__ __forceinline__ void few_place(typename C::S* U, const typename C::S*
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                   uint32_t* PS1, int64_t n, int M, const Ctl* ctl,
-                                                  const RunTile* rdesc) {
+                                                  const RunTile* rdesc, unsigned long long* tdesc = nullptr) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename TS::Smem sm;
@@ -1097,8 +1097,11 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
     const int64_t base = (int64_t)blockIdx.x * TS::T;
     if (base >= v.n) return;
     const int valid = (int)((v.n - base) < TS::T ? (v.n - base) : TS::T);
+    // the general plan's tiles describe themselves for merge slot 0's NEAR test
+    unsigned long long* desc =
+        (tdesc != nullptr && ctl != nullptr && ctl->path == SR_PATH_GENERAL) ? tdesc + 4 * blockIdx.x : nullptr;
     TS::run(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
-            valid);
+            valid, desc);
 }
 
 // Merge Path partition of merge slot k: co[c] = co-rank of the start of
@@ -1106,7 +1109,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
 template <class C>
 __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C::S* S1, int64_t n, int M,
                                                    int64_t T, int k, int CH, int64_t* co, const Ctl* ctl,
-                                                   const RunArea* ra) {
+                                                   const RunArea* ra, int near = 0) {
     using S = typename C::S;
     if (ra != nullptr && ctl != nullptr && ctl->path == SR_PATH_RUNS) {
         // RUNS: co-rank of every chunk of the pass inside its leaf group
@@ -1119,7 +1122,8 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
         }
         return;
     }
-    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k);
+    const bool near_on = near != 0 && ctl->force_path != SR_PATH_GENERAL;
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k, near_on);
     if (!v.active) return;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (c * CH >= v.n) return;
@@ -1143,7 +1147,8 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
                                               int64_t n, int M, int64_t T, int k, const Ctl* ctl,
-                                              const RunArea* ra, const FewTable* ft) {
+                                              const RunArea* ra, const FewTable* ft,
+                                              const unsigned long long* tdesc = nullptr) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename MC::Smem sm;
@@ -1161,7 +1166,15 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
             }
         }
     }
-    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
+    const bool near_on = tdesc != nullptr && ctl->force_path != SR_PATH_GENERAL;
+    if (near_on && k == 0 && ctl->path == SR_PATH_GENERAL) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k, near_on);
+    const int64_t nch = v.active ? (v.n + MC::CH - 1) / MC::CH : 0;
+    if (v.cn > 0 && (int64_t)blockIdx.x >= nch) {
+        // workgroups past the merge's chunks copy (the grid has at least T / CH of them)
+        copy_part(v.csrc, v.cdst, v.cpsrc, v.cpdst, v.cn, (int64_t)blockIdx.x - nch, (int64_t)gridDim.x - nch);
+        return;
+    }
     if (!v.active) return;
     const int64_t out0 = (int64_t)blockIdx.x * MC::CH;
     if (out0 >= v.n) return;
@@ -1176,7 +1189,7 @@ template <class C, int WG, int IT, bool PAIRS, bool NT = false>
 __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
                                                       const int64_t* co, const Ctl* ctl, const RunArea* ra,
-                                                      const FewTable* ft) {
+                                                      const FewTable* ft, const unsigned long long* tdesc = nullptr) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
     using MC = typename MP::MC;
     using S = typename C::S;
@@ -1198,7 +1211,10 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
             }
         }
     }
-    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
+    const bool near_on = tdesc != nullptr && ctl->force_path != SR_PATH_GENERAL;
+    if (near_on && k == 0 && ctl->path == SR_PATH_GENERAL) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k, near_on);
+    if (v.cn > 0) copy_part(v.csrc, v.cdst, v.cpsrc, v.cpdst, v.cn, (int64_t)blockIdx.x, (int64_t)gridDim.x);
     if (!v.active) return;
     MP::template run<NT>(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
 }
@@ -1632,7 +1648,7 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
     }
     if (tid == 0) {
         const unsigned long long total = s_base;
-        const bool fail = s_bad != 0 || ctl->bad_join != 0 || total > (unsigned long long)n;
+        const bool fail = s_bad != 0 || ld_agent(&ctl->bad_join) != 0 || total > (unsigned long long)n;
         const int64_t m = n - (int64_t)total;
         if (fail || m > n / 2) {
             ctl->path = SR_PATH_GENERAL;
@@ -1830,7 +1846,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         unsigned int* gc = reinterpret_cast<unsigned int*>(slots + kProbeMaxGrid * 4) + g * 64;
         last = false;
         if (atomicAdd(gc, 1u) == in_g - 1) {
-            *gc = 0u;  // reset for the next call (no other workgroup of this group touches it again)
+            st_agent(gc, 0u);  // reset for the next call (no other workgroup of this group touches it again)
             last = atomicAdd(&ctl->ticket, 1u) == groups - 1;
         }
     }
@@ -2001,7 +2017,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             __syncthreads();
             if (ns >= 0) {
                 for (int b = tid; b < kFewCopies * (2 * ns + 1); b += kProbeWG)
-                    ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)] = 0;
+                    st_agent(&ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)], 0ull);
                 if (tid == 0) ft->ns = (unsigned long long)ns;
                 path = SR_PATH_FEW;
             } else {
@@ -2015,12 +2031,13 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             ctl->reserved[1] = s_asc;
             ctl->reserved[2] = 0;
             ctl->reserved[3] = 0;
-            ctl->mixed = 0;
-            ctl->ticket = 0;
-            ctl->m = 0;
+            st_agent(&ctl->mixed, 0u);
+            st_agent(&ctl->ticket, 0u);
+            st_agent(&ctl->m, 0ull);
             ctl->job_passes = 0;
             ctl->n_kept = 0;
-            ctl->bad_join = 0;
+            st_agent(&ctl->bad_join, 0u);
+            st_agent(&ctl->near_bad, 0u);
             ctl->ticket2 = 0;
             unsigned int ep = (ctl->epoch + 1u) & 0xFFFFFFu;
             ctl->epoch = ep == 0u ? 1u : ep;
@@ -2373,6 +2390,7 @@ bool g_profile = false;
 bool g_outlier_enabled = true;  // allow the OUTLIER path for keys-only sorts
 bool g_runs_enabled = true;     // allow the RUNS path for keys-only sorts
 bool g_few_enabled = true;      // allow the FEW path for keys-only sorts
+bool g_near_enabled = true;     // allow the NEAR plan on general sorts
 // Launch-shape options; the "auto" value defers to the tuning table, then to
 // the built-in rule in resolve_shape.
 int64_t g_partition_min_n = -1;  // separate Merge Path partition launch from this n on
@@ -2380,6 +2398,7 @@ int g_tile_variant = -1;         // 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
 int g_merge_items = 0;           // fused merge: outputs per thread, 8 or 16 (32-bit keys only)
 int g_nontemporal = -1;          // persistent merge: nontemporal window loads and stores
 std::vector<sr_tune_entry> g_tune;  // sorted by (dtype, pairs, min_n)
+uint64_t g_tune_version = 0;        // bumped by every sr_tune_set (captured graphs key on it)
 
 // Built-in rules, from a sweep of random keys of each type on gfx950.
 constexpr int64_t kPartitionMinN = (int64_t)1 << 23;
@@ -2409,7 +2428,7 @@ struct LaunchShape {
 LaunchShape resolve_shape(int dt, bool pairs, int64_t n, size_t key_bytes) {
     const sr_tune_entry* row = nullptr;
     for (const sr_tune_entry& e : g_tune)
-        if (e.dtype == dt && e.pairs == (pairs ? 1 : 0) && e.min_n <= n) row = &e;
+        if (e.dtype == dt && e.pairs == (pairs ? 1 : 0) && e.segmented == 0 && e.min_n <= n) row = &e;
     LaunchShape sh;
     if (g_partition_min_n >= 0) sh.partition = n >= g_partition_min_n;
     else if (row && row->partition >= 0) sh.partition = row->partition != 0;
@@ -2424,6 +2443,28 @@ LaunchShape resolve_shape(int dt, bool pairs, int64_t n, size_t key_bytes) {
     else if (row && row->nontemporal >= 0) sh.nt = row->nontemporal != 0;
     else if (!pairs) sh.nt = (size_t)n * key_bytes >= kNontemporalBytes;
     else sh.nt = key_bytes == 8 && (size_t)n * key_bytes >= kNontemporalBytes / 2;  // not for 32-bit pairs
+    return sh;
+}
+
+// Shape of a segmented / batched sort (32-bit keys, keys only): the tile
+// sort's thread shape and the merge's outputs per thread.  Explicit options
+// first, then the table's segmented row of (dt, pairs) with the largest
+// min_n <= total keys, then the built-in shape (512 x 16 tiles, 16 outputs).
+struct SegShape {
+    int tile_variant;
+    int merge_items;
+};
+SegShape resolve_seg_shape(int dt, bool pairs, int64_t n) {
+    const sr_tune_entry* row = nullptr;
+    for (const sr_tune_entry& e : g_tune)
+        if (e.dtype == dt && e.pairs == (pairs ? 1 : 0) && e.segmented == 1 && e.min_n <= n) row = &e;
+    SegShape sh;
+    if (g_tile_variant >= 0) sh.tile_variant = g_tile_variant;
+    else if (row && row->tile_variant >= 0) sh.tile_variant = row->tile_variant;
+    else sh.tile_variant = 0;
+    if (g_merge_items > 0) sh.merge_items = g_merge_items;
+    else if (row && row->merge_items > 0) sh.merge_items = row->merge_items;
+    else sh.merge_items = 16;
     return sh;
 }
 
@@ -2448,13 +2489,21 @@ hipEvent_t get_event() {
     return e;
 }
 
+// Set while a call is recorded into a stream capture: no event records then.
+thread_local bool t_no_profile = false;
+struct NoProfile {
+    bool prev;
+    explicit NoProfile(bool on) : prev(t_no_profile) { t_no_profile = prev || on; }
+    ~NoProfile() { t_no_profile = prev; }
+};
+
 // Records an event pair around one launch when profiling is on.
 struct ProfScope {
     hipStream_t st;
     const char* name;
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(hipStream_t s, const char* nm) : st(s), name(nm) {
-        if (g_profile) {
+        if (g_profile && !t_no_profile) {
             std::lock_guard<std::mutex> lk(g_mu);
             a = get_event();
             b = get_event();
@@ -2504,6 +2553,7 @@ struct LastCall {
     int es = 0;
     int merge_passes = 0;
     int trivial = 1;
+    bool near = false;    // the NEAR plan was possible
     Ctl* ctl = nullptr;
 };
 
@@ -2617,6 +2667,19 @@ sr_status get_workspace(hipStream_t st, size_t data_bytes, Workspace** out, size
     return SR_OK;
 }
 
+// Whether (device, stream) already holds a workspace of these sizes, so a
+// call would allocate nothing.
+bool workspace_fits(hipStream_t st, size_t data_bytes, size_t aux_bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find({dev, st});
+    if (it == g_ws.end() || it->second == nullptr) return false;
+    const Workspace* ws = it->second;
+    const size_t need = round_up(std::max(data_bytes, (size_t)256), 256);
+    return ws->hdr != nullptr && ws->bytes >= need && ws->aux_bytes >= aux_bytes;
+}
+
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Look-back space of a sort of n keys with every presortedness path on (tile
@@ -2626,7 +2689,7 @@ size_t aux_bound(int64_t n) {
     const size_t ncls = (size_t)cdiv(n, kClsTC);
     const size_t cls_arr = round_up(round_up(ncls, (size_t)kVerRound) * 8, 256);
     return 4 * cls_arr + round_up(ncls * (kClsTC / 8), 256) + round_up(ncls * sizeof(RunTile), 256) +
-           round_up(sizeof(RunArea), 256);
+           round_up(sizeof(RunArea), 256) + round_up((size_t)cdiv(n, 4096) * 32, 256);
 }
 
 void* ws_data(Workspace* ws) { return ws->base; }
@@ -2652,6 +2715,13 @@ struct NoAllocDevice {
 };
 NoAllocDevice g_noalloc[kNoAllocMaxDevices];
 std::mutex g_noalloc_mu;
+
+bool noalloc_ready() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return false;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc[dev].ready;
+}
 
 // The device's allocation-free workspace; the first call on a device looks up
 // the array's address, zeroes its header and look-back space on `st` and
@@ -2737,16 +2807,15 @@ template <class C, bool PAIRS>
 sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool prepare_only = false,
                     hipStream_t ls = nullptr, bool noalloc = false) {
     if (ls == nullptr) ls = st;
+    // Recorded into the caller's stream capture, the sort enqueues the same
+    // launches (replays sort whatever the buffers hold then); it must neither
+    // allocate nor synchronize, so its workspace has to be in place already.
+    bool capturing = false;
     {
-        // a plain sort recorded into the caller's stream capture would be
-        // replayed by the graph executor, whose replays of this launch
-        // sequence were not reliable here: refuse it before anything is
-        // enqueued (the segmented entry point captures its own graphs)
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
-            return fail(SR_ERR_UNSUPPORTED, "plain sorts cannot be recorded into a stream capture; "
-                                            "sr_sort_segmented with the graph option captures its own graph");
+        capturing = hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
     }
+    NoProfile np(capturing);
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
     constexpr int T = TN::TWG * TN::TIT;
@@ -2791,9 +2860,20 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     // run descriptors and the run plan
     const size_t rdesc_bytes = runs_ok ? round_up((size_t)ncls * sizeof(RunTile), 256) : 0;
     const size_t rarea_bytes = runs_ok ? round_up(sizeof(RunArea), 256) : 0;
+    // NEAR: four codes per sorted tile for merge slot 0's test
+    bool near_ok;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        near_ok = g_near_enabled && M >= 3;
+    }
+    const size_t tdesc_bytes = near_ok ? round_up((size_t)ntiles * 32, 256) : 0;
     const size_t data_need = co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0);
-    const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes;
+    const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes + tdesc_bytes;
     sr_status s;
+    if (capturing && !(noalloc ? noalloc_ready() : workspace_fits(st, data_need, aux_need)))
+        return fail(SR_ERR_UNSUPPORTED, "a sort recorded into a stream capture cannot allocate or synchronize: "
+                                        "size the stream's workspace first (sr_reserve, or one sort of this "
+                                        "size on the stream before the capture)");
     if (noalloc) {
         s = noalloc_workspace(st, &ws);
         if (s == SR_OK && (data_need > ws->bytes || aux_need > ws->aux_bytes))
@@ -2818,6 +2898,10 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     RunTile* rdesc = nullptr;
     RunArea* rarea = nullptr;
     FewTable* ftab = few_ok ? reinterpret_cast<FewTable*>(static_cast<char*>(ws->hdr) + kFewOff) : nullptr;
+    unsigned long long* tdesc =
+        near_ok ? reinterpret_cast<unsigned long long*>(static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes +
+                                                        rdesc_bytes + rarea_bytes)
+                : nullptr;
 
     {
         ProfScope ps(ls, "probe");
@@ -2870,13 +2954,13 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
             if (sh.tile_variant == 1) {
                 hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
-                                   skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc);
+                                   skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc);
                 SR_LAUNCH_CHECK("tile_sort");
                 goto tile_done;
             }
         }
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, ls,
-                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc);
+                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc);
         SR_LAUNCH_CHECK("tile_sort");
     }
 tile_done:
@@ -2892,7 +2976,8 @@ tile_done:
             {
                 ProfScope ps(ls, "partition");
                 hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, ls, keys, skeys,
-                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea);
+                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea,
+                                   near_ok ? 1 : 0);
                 SR_LAUNCH_CHECK("partition");
             }
             ProfScope ps(ls, "merge");
@@ -2901,7 +2986,7 @@ tile_done:
             const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
             hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
                                (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
-                               (const FewTable*)ftab);
+                               (const FewTable*)ftab, (const unsigned long long*)tdesc);
             SR_LAUNCH_CHECK("merge");
         } else {
             ProfScope ps(ls, "merge");
@@ -2916,19 +3001,22 @@ tile_done:
                 if (merge8) {
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)(cdiv(n, TN::MWG * 8) + extra)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
-                                       (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab);
+                                       (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
+                                       (const unsigned long long*)tdesc);
                     done = true;
                 }
             }
             if (!done)
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)(nchunks + extra)),
                                    dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
-                                   (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab);
+                                   (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
+                                   (const unsigned long long*)tdesc);
             SR_LAUNCH_CHECK("merge");
         }
     }
     if (noalloc) return SR_OK;
     lc.trivial = 0;
+    lc.near = near_ok;
     lc.ctl = ctl;
     lc.tile = T;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -2946,7 +3034,15 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     using S = typename C::S;
     using TN = Tune<C, PAIRS>;
     constexpr int T = TN::TWG * TN::TIT;
-    constexpr int CH = TN::MWG * TN::MIT;
+    // 32-bit keys-only batches take their launch shape from the table
+    constexpr bool kShaped = sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8 && TN::MIT == 16;
+    SegShape sh{0, TN::MIT};
+    if constexpr (kShaped) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sh = resolve_seg_shape(DtypeOf<C>::value, PAIRS, n);
+    }
+    const bool merge8 = kShaped && sh.merge_items == 8;
+    const int CH = TN::MWG * (merge8 ? 8 : TN::MIT);
     S* keys = static_cast<S*>(keys_v);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
     const size_t pbytes = PAIRS ? round_up((size_t)n * 4, 256) : 0;
@@ -2974,14 +3070,24 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
     {
         ProfScope ps(ls, "seg_tile_sort");
         auto kern = k_seg_tile<C, TN::TWG, TN::TIT, PAIRS>;
-        const int64_t grid = std::min<int64_t>(cdiv(n, T) + nseg, resident_blocks(kern, TN::TWG));
-        hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(TN::TWG), 0, ls, keys, skeys, pay,
+        int threads = TN::TWG;
+        if constexpr (kShaped) {
+            if (sh.tile_variant == 1) {
+                kern = k_seg_tile<C, 1024, 8, PAIRS>;
+                threads = 1024;
+            }
+        }
+        const int64_t grid = std::min<int64_t>(cdiv(n, T) + nseg, resident_blocks(kern, threads));
+        hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(threads), 0, ls, keys, skeys, pay,
                            spay, off, nseg, (const int64_t*)tile_pre, (const int*)seg_passes, (const SegCtl*)sc,
                            sptrs);
         SR_LAUNCH_CHECK("seg_tile_sort");
     }
     const int Mbound = ceil_log2(cdiv(n, T));
     auto mk = k_seg_merge<C, TN::MWG, TN::MIT, PAIRS>;
+    if constexpr (kShaped) {
+        if (merge8) mk = k_seg_merge<C, TN::MWG, 8, PAIRS>;
+    }
     const int64_t mgrid = std::max<int64_t>(1, std::min<int64_t>(cdiv(n, CH) + nseg, resident_blocks(mk, TN::MWG)));
     for (int k = 0; k < Mbound; ++k) {
         ProfScope ps(ls, "seg_merge");
@@ -2998,13 +3104,14 @@ sr_status seg_impl(void* keys_v, uint32_t* pay, int64_t n, const int64_t* off, i
 // generation) and replayed afterwards with one hipGraphLaunch.  The plan
 // stays on the device, so a replay adapts to new data in the same buffers.
 bool g_graph = false;
+bool g_graph_plain = false;  // plain sorts captured too (both need "graph")
 
 struct GraphKey {
     int kind, dt, dev;
     const void *keys, *pay, *off;
     int64_t n, nseg;
     hipStream_t st;
-    int64_t opts[6];
+    int64_t opts[10];
     unsigned long long gen;
     bool operator<(const GraphKey& o) const {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
@@ -3056,6 +3163,10 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
         key.opts[3] = g_tile_variant;
         key.opts[4] = g_merge_items;
         key.opts[5] = g_nontemporal;
+        key.opts[6] = g_runs_enabled;
+        key.opts[7] = g_few_enabled;
+        key.opts[8] = (int64_t)g_tune_version;
+        key.opts[9] = g_near_enabled;
         auto it = g_ws.find({key.dev, st});
         key.gen = it != g_ws.end() && it->second ? it->second->generation : 0;
     }
@@ -3107,14 +3218,21 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
     return SR_OK;
 }
 
-// Plain sorts are always launched directly: replays of a captured GENERAL
-// sequence (tile sort feeding the merge passes) gave wrong results on this
-// platform's graph executor, so the "graph" option applies to the segmented
-// entry point only (whose replays are checked against direct launches).
+// Plain sorts go through the private-capture graph cache only when both the
+// "graph" and "graph_plain" options are on (the segmented entry point needs
+// "graph" alone); otherwise they launch directly on the caller's stream.
 template <class C, bool PAIRS>
 sr_status sort_dispatch(int dt, void* keys, uint32_t* pay, int64_t n, hipStream_t st) {
-    (void)dt;
-    return sort_impl<C, PAIRS>(keys, pay, n, st);
+    bool plain_graphs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        plain_graphs = g_graph_plain;
+    }
+    if (!plain_graphs) return sort_impl<C, PAIRS>(keys, pay, n, st);
+    return run_maybe_graph(
+        PAIRS ? 1 : 0, dt, keys, pay, nullptr, n, 0, st,
+        [&](hipStream_t ls) { return sort_impl<C, PAIRS>(keys, pay, n, st, false, ls); },
+        [&]() { return sort_impl<C, PAIRS>(keys, pay, n, st, true); });
 }
 
 template <class C, bool PAIRS>
@@ -3440,6 +3558,14 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             break;
         }
         default:
+            if (h.path == SR_PATH_GENERAL && lc.near && h.near_bad == 0 && h.force_path != SR_PATH_GENERAL) {
+                // tile sort, two neighbour rounds, and a copy back when the
+                // second round had to write the partner buffer
+                out->path = SR_PATH_NEAR;
+                out->merge_passes = 2 + (lc.merge_passes & 1);
+                eq = 1 + out->merge_passes;
+                break;
+            }
             out->merge_passes = lc.merge_passes;
             eq = 1 + lc.merge_passes;
             break;
@@ -3485,6 +3611,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
         g_graph = value != 0;
         return SR_OK;
     }
+    if (std::strcmp(name, "graph_plain") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "graph_plain is 0 or 1");
+        g_graph_plain = value != 0;
+        return SR_OK;
+    }
     if (std::strcmp(name, "tile_variant") == 0) {
         if (value < -1 || value > 1) return fail(SR_ERR_INVALID_ARGUMENT, "tile_variant is -1, 0 or 1");
         g_tile_variant = (int)value;
@@ -3504,6 +3635,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (std::strcmp(name, "outlier_path") == 0) {
         if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "outlier_path is 0 or 1");
         g_outlier_enabled = value != 0;
+        return SR_OK;
+    }
+    if (std::strcmp(name, "near_path") == 0) {
+        if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "near_path is 0 or 1");
+        g_near_enabled = value != 0;
         return SR_OK;
     }
     if (std::strcmp(name, "few_path") == 0) {
@@ -3542,18 +3678,24 @@ sr_status sr_tune_set(const sr_tune_entry* entries, int64_t count) {
         if (e.partition < -1 || e.partition > 1) return fail(SR_ERR_INVALID_ARGUMENT, at + "partition is -1, 0 or 1");
         if (e.nontemporal < -1 || e.nontemporal > 1)
             return fail(SR_ERR_INVALID_ARGUMENT, at + "nontemporal is -1, 0 or 1");
+        if (e.segmented != 0 && e.segmented != 1) return fail(SR_ERR_INVALID_ARGUMENT, at + "segmented is 0 or 1");
+        if (e.segmented && (e.partition != -1 || e.nontemporal != -1))
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "segmented rows leave partition and nontemporal unset");
+        if (e.pad != 0) return fail(SR_ERR_INVALID_ARGUMENT, at + "pad is 0");
     }
     auto before = [](const sr_tune_entry& a, const sr_tune_entry& b) {
         if (a.dtype != b.dtype) return a.dtype < b.dtype;
         if (a.pairs != b.pairs) return a.pairs < b.pairs;
+        if (a.segmented != b.segmented) return a.segmented < b.segmented;
         return a.min_n < b.min_n;
     };
     std::sort(rows.begin(), rows.end(), before);
     for (size_t i = 1; i < rows.size(); ++i)
         if (!before(rows[i - 1], rows[i]))
-            return fail(SR_ERR_INVALID_ARGUMENT, "two tuning rows with the same dtype, pairs and min_n");
+            return fail(SR_ERR_INVALID_ARGUMENT, "two tuning rows with the same dtype, pairs, segmented and min_n");
     std::lock_guard<std::mutex> lk(g_mu);
     g_tune.swap(rows);
+    ++g_tune_version;
     return SR_OK;
 }
 

@@ -163,7 +163,11 @@ struct TileSort {
         }
     }
 
-    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid) {
+    // desc (optional): the sorted tile's codes at positions 0, valid-1, T/2-1
+    // and T/2 (the last two only when the tile holds more than T/2 keys), for
+    // the NEAR test of the general plan.
+    static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid,
+                               unsigned long long* desc = nullptr) {
         const int tid = threadIdx.x;
         E v[IT];
         const bool vec = valid == T && aligned16(src) && (!PAIRS || aligned16(psrc));
@@ -202,6 +206,11 @@ struct TileSort {
         }
         __syncthreads();
 
+        if (desc != nullptr && tid < 4) {
+            constexpr int H = T / 2;
+            const int pos = tid == 0 ? 0 : tid == 1 ? valid - 1 : tid == 2 ? H - 1 : H;
+            if (tid < 2 || valid > H) desc[tid] = (unsigned long long)sm.k[pad(pos)];
+        }
         // store, striped so that consecutive lanes write consecutive addresses
         const bool vout = valid == T && aligned16(dst);
         if (vout) {
@@ -617,6 +626,57 @@ struct MergePersistent {
     }
 };
 
+// ============================================================ NEAR plan
+// Part `part` of `parts` of a copy of cn keys (and payloads when psrc is
+// set): 16-byte vectors where both sides are aligned, else elements.
+template <class S>
+__device__ __forceinline__ void copy_part(const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int64_t cn,
+                                          int64_t part, int64_t parts) {
+    constexpr int VN = 16 / (int)sizeof(S);
+    const int64_t per = ((cn + parts - 1) / parts + 63) / 64 * 64;
+    const int64_t a = part * per;
+    const int64_t b = (a + per) < cn ? (a + per) : cn;
+    if (a >= b) return;
+    if (aligned16(src + a) && aligned16(dst + a)) {
+        const int64_t nv = (b - a) / VN;
+        const V16<S>* s16 = reinterpret_cast<const V16<S>*>(src + a);
+        V16<S>* d16 = reinterpret_cast<V16<S>*>(dst + a);
+        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) d16[i] = s16[i];
+        for (int64_t i = a + nv * VN + threadIdx.x; i < b; i += blockDim.x) dst[i] = src[i];
+    } else {
+        for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) dst[i] = src[i];
+    }
+    if (psrc != nullptr)
+        for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) pdst[i] = psrc[i];
+}
+
+// Merge slot 0 of the general plan checks whether the two-round NEAR plan
+// sorts the array, from the sorted tiles' descriptors (codes at 0, last,
+// T/2-1, T/2): for every tile t, (a) last(t) <= first(t+2); (b) at most T/2
+// keys of tile t+1 are below last(t): key T/2 of t+1 >= last(t) (or t+1 holds
+// at most T/2 keys); (c) at most T/2 keys of tile t are above first(t+1): key
+// T/2-1 of t <= first(t+1).  Then after the rounds (0,1),(2,3),... and
+// (1,2),(3,4),... of T-blocks every block boundary is in order.  A
+// violation anywhere sets near_bad (reset by the probe).
+__device__ __forceinline__ void near_check(Ctl* ctl, const unsigned long long* td, int64_t n, int64_t T) {
+    const int64_t ntiles = (n + T - 1) / T;
+    const int64_t H = T / 2;
+    bool bad = false;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long* d = td + 4 * t;
+        if (t + 2 < ntiles && d[1] > td[4 * (t + 2)]) bad = true;
+        if (t + 1 < ntiles) {
+            const unsigned long long* e = d + 4;
+            const int64_t next_len = (n - (t + 1) * T) < T ? (n - (t + 1) * T) : T;
+            if (next_len > H && e[3] < d[1]) bad = true;   // tile t is whole: key H-1 exists
+            if (d[2] > e[0]) bad = true;
+        }
+    }
+    if (__builtin_amdgcn_ballot_w64(bad) != 0ull && __lane_id() == 0 && ld_agent(&ctl->near_bad) == 0u)
+        atomicOr(&ctl->near_bad, 1u);
+}
+
 // ============================================================ job views
 // The launch sequence is fixed on the host; which data a launch works on is
 // read from the plan in the control block.  GENERAL sorts the user buffer U
@@ -634,15 +694,59 @@ struct PassView {
     int64_t width;
     int64_t split;
     bool active;
+    // a plain copy of cn keys (and payloads) from csrc to cdst in the same slot
+    const S* csrc;
+    S* cdst;
+    const uint32_t* cpsrc;
+    uint32_t* cpdst;
+    int64_t cn;
 };
+
+// NEAR (on the general plan, decided by merge slot 0 from the tile
+// descriptors): slot 1 merges the T-blocks (1,2), (3,4), ... of slot 0's
+// output -- the array viewed from offset T, in groups of two blocks -- and
+// copies block 0; it writes U when slot 0 wrote S1 (M even), else S1, and then
+// slot 2 copies S1 back to U.  Later slots do nothing.
+__device__ __forceinline__ bool near_taken(const Ctl* ctl, bool near_on) {
+    return near_on && ld_agent(&ctl->near_bad) == 0u;
+}
 
 template <class S>
 __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
-                                                     int64_t n, int M, int64_t T, int k) {
+                                                     int64_t n, int M, int64_t T, int k, bool near_on = false) {
     PassView<S> v{};
     v.active = false;
     v.split = -1;
+    v.cn = 0;
     const int path = ctl->path;
+    if (path == 3 /* SR_PATH_GENERAL */ && k >= 1 && near_taken(ctl, near_on)) {
+        const bool to_s1 = (M & 1) == 0;  // slot 0 wrote S1
+        S* X = to_s1 ? S1 : U;
+        S* Y = to_s1 ? U : S1;
+        uint32_t* PX = to_s1 ? PS1 : PU;
+        uint32_t* PY = to_s1 ? PU : PS1;
+        if (k == 1) {
+            v.src = X + T;
+            v.dst = Y + T;
+            v.psrc = PX ? PX + T : nullptr;
+            v.pdst = PY ? PY + T : nullptr;
+            v.n = n - T;
+            v.width = T;
+            v.active = true;
+            v.csrc = X;
+            v.cdst = Y;
+            v.cpsrc = PX;
+            v.cpdst = PY;
+            v.cn = T;
+        } else if (k == 2 && !to_s1) {
+            v.csrc = S1;
+            v.cdst = U;
+            v.cpsrc = PS1;
+            v.cpdst = PU;
+            v.cn = n;
+        }
+        return v;
+    }
     if (path == 3 /* SR_PATH_GENERAL */) {
         const int from = (M - k) & 1;
         v.src = from ? S1 : U;

@@ -185,18 +185,17 @@ def sharp_teeth(n: int, k: int) -> np.ndarray:
 
 def shuffled_teeth(n: int, k: int, seed: int) -> np.ndarray:
     """The k sections of a k-sharp teeth list interleaved at random, each
-    section keeping its own order (a uniformly random interleaving: a
-    Fisher-Yates shuffle of the section labels)."""
+    section keeping its own order: the section labels, one per key, are put in
+    a uniformly random order (sorted by seeded 64-bit random keys, ties by
+    position), and the keys of section s fill the positions labelled s in
+    turn."""
     a = sharp_teeth(n, k)
     b = _sections(n, k)
     labels = np.repeat(np.arange(k, dtype=np.int64), np.diff(b))
-    r = stream(seed, n)
-    for i in range(n - 1, 0, -1):
-        j = int(below(r[i:i + 1], i + 1)[0])
-        labels[i], labels[j] = labels[j], labels[i]
+    labels = labels[np.argsort(stream(seed, n), kind="stable")]
     out = np.empty(n, dtype=np.int32)
-    for s in range(k):
-        out[labels == s] = a[b[s]:b[s + 1]]
+    # positions grouped by label, in increasing position order within a label
+    out[np.argsort(labels, kind="stable")] = a
     return out
 
 

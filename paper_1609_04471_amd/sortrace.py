@@ -23,7 +23,7 @@ TUNE_TABLE = os.path.join(_HERE, "tune_gfx950.json")
 
 SR_INT32, SR_UINT64, SR_FLOAT32 = 0, 1, 2
 DTYPES = {"int32": SR_INT32, "uint64": SR_UINT64, "float32": SR_FLOAT32}
-PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general", 4: "runs", 5: "few"}
+PATHS = {-1: "trivial", 0: "sorted", 1: "reversed", 2: "outlier", 3: "general", 4: "runs", 5: "few", 6: "near"}
 STATUS = {0: "SR_OK", 1: "SR_ERR_INVALID_ARGUMENT", 2: "SR_ERR_UNSUPPORTED",
           3: "SR_ERR_OUT_OF_MEMORY", 4: "SR_ERR_DEVICE", 5: "SR_ERR_INTERNAL"}
 
@@ -63,7 +63,8 @@ class SrRequestRecord(ctypes.Structure):
 class SrTuneEntry(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("pairs", ctypes.c_int32), ("min_n", ctypes.c_int64),
                 ("tile_variant", ctypes.c_int32), ("merge_items", ctypes.c_int32),
-                ("partition", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+                ("partition", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("segmented", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class SrPresortedness(ctypes.Structure):
@@ -111,7 +112,7 @@ def load(path: str = LIB_PATH):
     lib.sr_release_stream.argtypes = [vp]
     lib.sr_set_workspace.argtypes = [vp, sz, vp]
     lib.sr_server_create.argtypes = [ctypes.POINTER(SrServerConfig), ctypes.POINTER(vp)]
-    lib.sr_server_submit.argtypes = [vp, i32, vp, sz, ctypes.c_uint64, ctypes.c_double]
+    lib.sr_server_submit.argtypes = [vp, i32, vp, sz, ctypes.c_uint64, ctypes.c_double, vp]
     lib.sr_server_now.argtypes = [vp]
     lib.sr_server_wait_idle.argtypes = [vp, ctypes.c_double]
     lib.sr_server_records.argtypes = [vp, ctypes.POINTER(SrRequestRecord), sz, ctypes.POINTER(sz)]
@@ -290,13 +291,15 @@ def set_option(name: str, value: int) -> None:
 
 def tune_set(rows) -> None:
     """Replace the tuning table.  rows: dicts with dtype ("int32", "uint64",
-    "float32"), pairs (bool), min_n and any of TUNE_FIELDS (missing = unset)."""
+    "float32"), pairs (bool), segmented (bool, default False), min_n and any of
+    TUNE_FIELDS (missing = unset)."""
     lib = load()
     buf = (SrTuneEntry * max(1, len(rows)))()
     for i, r in enumerate(rows):
         e = buf[i]
         e.dtype = DTYPES[r["dtype"]]
         e.pairs = int(bool(r.get("pairs", False)))
+        e.segmented = int(bool(r.get("segmented", False)))
         e.min_n = int(r.get("min_n", 0))
         for f in TUNE_FIELDS:
             setattr(e, f, int(r.get(f, TUNE_UNSET[f])))
@@ -304,14 +307,14 @@ def tune_set(rows) -> None:
 
 
 def tune_get() -> list:
-    """The tuning table as a list of dicts (sorted by dtype, pairs, min_n)."""
+    """The tuning table as a list of dicts (sorted by dtype, pairs, segmented, min_n)."""
     lib = load()
     cnt = ctypes.c_int64()
     _check(lib.sr_tune_get(None, 0, ctypes.byref(cnt)), "sr_tune_get")
     buf = (SrTuneEntry * max(1, cnt.value))()
     _check(lib.sr_tune_get(buf, cnt.value, ctypes.byref(cnt)), "sr_tune_get")
     names = {v: k for k, v in DTYPES.items()}
-    return [{"dtype": names[e.dtype], "pairs": bool(e.pairs), "min_n": e.min_n,
+    return [{"dtype": names[e.dtype], "pairs": bool(e.pairs), "segmented": bool(e.segmented), "min_n": e.min_n,
              **{f: getattr(e, f) for f in TUNE_FIELDS}} for e in buf[:cnt.value]]
 
 
@@ -359,13 +362,26 @@ class Server:
         h = ctypes.c_void_p()
         _check(self._lib.sr_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sr_server_create")
         self._h = h
+        self._events = {}
 
     def now(self) -> float:
         return self._lib.sr_server_now(self._h)
 
-    def submit(self, keys, tag: int, t_arrive: float, dtype: str | None = None):
+    def submit(self, keys, tag: int, t_arrive: float, dtype: str | None = None, ready="current"):
+        """ready: "current" records an event on the current stream now, so the
+        sort waits for work already queued there on the keys; None skips the
+        wait; or a torch.cuda.Event the caller recorded."""
+        import torch
+        if isinstance(ready, str):
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream())
+        else:
+            ev = ready
+        raw = None if ev is None else ctypes.c_void_p(ev.cuda_event)
         _check(self._lib.sr_server_submit(self._h, _key_dtype(keys, dtype), _dev(keys, "keys"), keys.numel(),
-                                          tag, t_arrive), "sr_server_submit")
+                                          tag, t_arrive, raw), "sr_server_submit")
+        if ev is not None:
+            self._events[tag] = ev   # kept alive until the request is reported finished
 
     def wait_idle(self, timeout_s: float = 60.0):
         _check(self._lib.sr_server_wait_idle(self._h, timeout_s), "sr_server_wait_idle")
@@ -378,6 +394,7 @@ class Server:
             _check(self._lib.sr_server_records(self._h, buf, 4096, ctypes.byref(cnt)), "sr_server_records")
             for i in range(cnt.value):
                 r = buf[i]
+                self._events.pop(r.tag, None)
                 out.append({"tag": r.tag, "dtype": r.dtype, "batch": r.batch, "n": r.n, "status": r.status,
                             "t_arrive": r.t_arrive, "t_admit": r.t_admit, "t_launch": r.t_launch,
                             "t_done": r.t_done})
@@ -388,6 +405,7 @@ class Server:
         if self._h:
             self._lib.sr_server_destroy(self._h)
             self._h = None
+        self._events = {}
 
     def __enter__(self):
         return self

@@ -114,6 +114,20 @@ def test_tuning_table_validation(lib, keep_table):
         assert sortrace.tune_get() == got      # unchanged
     with pytest.raises(sortrace.SortraceError):
         sortrace.tune_set([rows[2], dict(rows[2], merge_items=8)])  # same (dtype, pairs, min_n)
+    # segmented rows: their own kind (same min_n as a plain row is fine), only
+    # tile_variant and merge_items
+    seg = dict(rows[2], segmented=True, tile_variant=0, merge_items=8)
+    sortrace.tune_set(rows + [seg])
+    both = sortrace.tune_get()
+    assert [(r["min_n"], r["segmented"]) for r in both if r["dtype"] == "int32"] == \
+        [(0, False), (1 << 22, False), (0, True)]
+    for r in (dict(seg, partition=1), dict(seg, nontemporal=0)):
+        with pytest.raises(sortrace.SortraceError):
+            sortrace.tune_set([r])
+    raw = (sortrace.SrTuneEntry * 1)()
+    raw[0].tile_variant, raw[0].partition, raw[0].nontemporal, raw[0].segmented = -1, -1, -1, 2
+    assert lib.sr_tune_set(raw, 1) == 1 and b"segmented" in lib.sr_last_error_message()
+    sortrace.tune_set(rows)
     e = (sortrace.SrTuneEntry * 1)()
     e[0].dtype = 9
     assert lib.sr_tune_set(e, 1) == 1 and b"dtype" in lib.sr_last_error_message()

@@ -337,10 +337,11 @@ def test_concurrent_host_threads(gpu):
 
 
 @pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")  # nothing was recorded: the point
-def test_plain_sort_refuses_stream_capture(gpu):
-    """A plain sort on a stream that is capturing into a graph is refused
-    with SR_ERR_UNSUPPORTED before anything is recorded; the keys stay as
-    they were and the same call sorts once the capture has ended."""
+def test_plain_sort_refuses_capture_that_would_allocate(gpu):
+    """On a stream without a workspace of the size, a plain sort recorded
+    into a capture is refused with SR_ERR_UNSUPPORTED before anything is
+    recorded; the keys stay as they were and the same call sorts once the
+    capture has ended."""
     lib = gpu.load()
     a = inputs.random_int32(100_003, seed=21)
     t = to_dev(a)
@@ -361,6 +362,71 @@ def test_plain_sort_refuses_stream_capture(gpu):
     gpu.sort_keys(t, dtype="int32", stream=st)
     st.synchronize()
     assert np.array_equal(from_dev(t, a), np.sort(a))
+    assert lib.sr_release_stream(st.cuda_stream) == 0
+
+
+@pytest.mark.parametrize("n", [300_001, 2_000_000, 9_000_001])
+def test_plain_sorts_recorded_into_a_stream_capture(gpu, n):
+    """Keys and pairs sorts recorded into a torch CUDA graph on a stream whose
+    workspace is reserved, replayed five times on new data of every input
+    type (each replay takes its own device plan), with eager sorts on the
+    same stream between the replays: every replay equals the oracle."""
+    lib = gpu.load()
+    st = torch.cuda.Stream()
+    assert lib.sr_reserve(0, n, 0, st.cuda_stream) == 0
+    keys = torch.empty(n, dtype=torch.int32, device=DEV)
+    pk = torch.empty(n, dtype=torch.int64, device=DEV)
+    pp = torch.empty(n, dtype=torch.int32, device=DEV)
+    other = torch.empty(n, dtype=torch.int32, device=DEV)
+    with torch.cuda.stream(st):   # warm-up sorts size the pairs workspace too
+        gpu.sort_pairs(pk, pp, dtype="uint64", stream=st)
+    st.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        g.capture_begin()
+        try:
+            gpu.sort_keys(keys, dtype="int32", stream=st)
+            gpu.sort_pairs(pk, pp, dtype="uint64", stream=st)
+        finally:
+            g.capture_end()
+    kinds = ["random", "reversed", "nearly", "few", "random"]
+    for rep, kind in enumerate(kinds):
+        a = inputs.int32_of_type(kind, n, 90 + rep)
+        hk, hp = inputs.runs_uint64(n, seed=rep, tie_stress=rep % 2 == 1)
+        with torch.cuda.stream(st):
+            keys.copy_(torch.from_numpy(a))
+            pk.copy_(torch.from_numpy(hk.view(np.int64)))
+            pp.copy_(torch.from_numpy(hp.view(np.int32)))
+            g.replay()
+            other.copy_(torch.from_numpy(inputs.random_int32(n, 7 + rep)))
+            gpu.sort_keys(other, dtype="int32", stream=st)
+        st.synchronize()
+        assert np.array_equal(from_dev(keys, a), oracle.sort_keys(a)), (rep, kind)
+        wk, wp = oracle.sort_pairs(hk, hp)
+        assert np.array_equal(pk.cpu().numpy().view(np.uint64), wk), rep
+        assert np.array_equal(pp.cpu().numpy().view(np.uint32), wp), rep
+    del g
+    torch.cuda.synchronize()
+    assert lib.sr_release_stream(st.cuda_stream) == 0
+
+
+def test_plain_sort_graph_cache(gpu):
+    """The library's own capture-and-replay cache for plain sorts ("graph" and
+    "graph_plain" options): repeated calls on one buffer with new data."""
+    n = 2_000_000
+    t = torch.empty(n, dtype=torch.int32, device=DEV)
+    gpu.set_option("graph", 1)
+    gpu.set_option("graph_plain", 1)
+    try:
+        for rep, kind in enumerate(["random", "few", "reversed", "nearly", "random", "few"]):
+            a = inputs.int32_of_type(kind, n, 40 + rep)
+            t.copy_(torch.from_numpy(a))
+            gpu.sort_keys(t, dtype="int32")
+            torch.cuda.synchronize()
+            assert np.array_equal(from_dev(t, a), oracle.sort_keys(a)), (rep, kind)
+    finally:
+        gpu.set_option("graph_plain", 0)
+        gpu.set_option("graph", 0)
 
 
 def test_random_sizes_sweep(gpu):

@@ -126,3 +126,29 @@ def test_shipped_table_is_valid_and_loaded(gpu):
         want = sorted(rows, key=lambda r: (gpu.DTYPES[r["dtype"]], r["pairs"], r["min_n"]))
         assert [(g["dtype"], g["pairs"], g["min_n"]) for g in got] == \
             [(w["dtype"], w["pairs"], w["min_n"]) for w in want]
+
+
+@pytest.mark.parametrize("tile_variant,merge_items", [(0, 8), (1, 8), (1, 16), (0, 16)])
+def test_segmented_rows_choose_the_batch_shape(clean, tile_variant, merge_items):
+    """A segmented row of the table sets the tile shape and merge outputs of
+    sr_sort_segmented / sr_sort_batch (32-bit keys): every shape sorts the
+    batched-workload mix exactly as the oracle."""
+    from paper_1609_04471_amd import sortrace
+    keys, off, _ = inputs.segments_int32(160, seed=12)
+    sortrace.tune_set([{"dtype": "int32", "pairs": False, "segmented": True, "min_n": 0,
+                        "tile_variant": tile_variant, "merge_items": merge_items}])
+    t = torch.from_numpy(keys.copy()).to("cuda:0")
+    sortrace.sort_segmented(t, torch.from_numpy(off).to("cuda:0"), dtype="int32")
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), oracle.sort_segmented(keys, off))
+    f = keys.astype(np.float32) * np.float32(0.5)
+    tf = torch.from_numpy(f.copy()).to("cuda:0")
+    sortrace.tune_set([{"dtype": "float32", "pairs": False, "segmented": True, "min_n": 0,
+                        "tile_variant": tile_variant, "merge_items": merge_items}])
+    arrays = [tf[int(off[i]):int(off[i + 1])] for i in range(0, 160, 7)]
+    sortrace.sort_batch(arrays, dtype="float32")
+    torch.cuda.synchronize()
+    got = tf.cpu().numpy()
+    for i in range(0, 160, 7):
+        a, b = int(off[i]), int(off[i + 1])
+        assert np.array_equal(got[a:b].view(np.uint32), oracle.sort_keys(f[a:b]).view(np.uint32))
