@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--no-lists", action="store_true", help="skip the heavy list items section")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--only", choices=["small", "big-random", "big-reversed", "big-nearly", "big-few", "seg", "serve",
-                                       "classes", "configs", "lists"],
+                                       "classes", "configs", "lists", "comparisons"],
                     default=None,
                     help="run one section only (for profiler runs)")
     args = ap.parse_args()
@@ -343,22 +343,11 @@ def main():
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu and args.only is None:
-        import oracle
-        hosts = {k: host_input(k, N_SMALL) for k in types}
-        done, t0 = 0, time.perf_counter()
-        rounds = 0
-        while True:
-            for k in types:
-                oracle.sort_keys(hosts[k])
-                done += N_SMALL
-            rounds += 1
-            el = time.perf_counter() - t0
-            if el > 12.0 or rounds >= 40:
-                break
-        cpu = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"{rounds} round(s) of the four 2M int32 inputs ({done} keys) through the "
-                         f"single-threaded oracle mergesort, {el:.1f} s"}
-        log(f"cpu baseline: {cpu}")
+        cpu = cpu_section(args, np, inputs, types, host_input)
+
+    comparisons = None
+    if not args.no_cpu and args.only in (None, "comparisons"):
+        comparisons = comparisons_section(np, inputs, types, host_input)
 
     line = {
         "metric": METRIC,
@@ -386,10 +375,142 @@ def main():
         "keys_2p20_and_pairs_2p24": result.get("configs"),
         "heavy_lists": result.get("lists"),
         "serving": result.get("serving"),
+        "paper_mergesort_comparisons": comparisons,
         "tuning": result.get("tuning"),
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_section(args, np, inputs, types, host_input):
+    """The CPU oracle timed on this host: (1) the single-threaded mergesort on
+    the four 2M inputs of the step (the reported value), (2) its task-parallel
+    variant on all usable cores, same inputs, (3) one single-threaded sort of
+    each 256M input, the four run side by side on four threads.  Every input
+    is the same seeded array the GPU sorts."""
+    import concurrent.futures as cf
+    import oracle
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    hosts = {k: host_input(k, N_SMALL) for k in types}
+    done, rounds, t0 = 0, 0, time.perf_counter()
+    while True:
+        for k in types:
+            oracle.sort_keys(hosts[k])
+            done += N_SMALL
+        rounds += 1
+        el = time.perf_counter() - t0
+        if el > 12.0 or rounds >= 40:
+            break
+    seeds = {k: inputs.seed_for(2, types.index(k), N_SMALL) for k in types}
+    cpu = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": 1, "kind": "oracle",
+           "sample": f"{rounds} round(s) of the four 2M int32 inputs ({done} keys) through the "
+                     f"single-threaded oracle mergesort, {el:.1f} s",
+           "nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": cpu_model(),
+           "seeds_2M": {k: hex(v) for k, v in seeds.items()}}
+    threads = max(1, min(usable, 64))
+    done, rounds, t0 = 0, 0, time.perf_counter()
+    while True:
+        for k in types:
+            oracle.sort_keys_parallel(hosts[k], threads)
+            done += N_SMALL
+        rounds += 1
+        el = time.perf_counter() - t0
+        if el > 6.0 or rounds >= 100:
+            break
+    t_used = 1 << (threads.bit_length() - 1)
+    cpu["parallel"] = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": t_used,
+                       "sample": f"{rounds} round(s) of the same four 2M inputs through the task-parallel "
+                                 f"variant of the oracle on {t_used} threads, {el:.1f} s"}
+    # the paper's own mergesort (Sec. 3 techniques, a CPU program) on the same inputs
+    import baseline
+    done, rounds, ncmp, t0 = 0, 0, 0, time.perf_counter()
+    while True:
+        for k in types:
+            _, c = baseline.sort(hosts[k])
+            done += N_SMALL
+            ncmp += c
+        rounds += 1
+        el = time.perf_counter() - t0
+        if el > 6.0 or rounds >= 100:
+            break
+    cpu["paper_mergesort"] = {"value": round(done / el / 1e6, 3), "unit": "Mkeys/s", "cores": 1,
+                              "comparisons_per_key": round(ncmp / done, 3),
+                              "minrun": baseline.MINRUN, "gallop_after": baseline.GALLOP_AFTER,
+                              "sample": f"{rounds} round(s) of the same four 2M inputs through the paper's "
+                                        f"mergesort (Sec. 3 (a), (b), (e2), (f), (g)) as a C program, {el:.1f} s"}
+    log(f"cpu baseline: {cpu}")
+    if not args.no_big:
+        def leg(k):
+            a = host_input(k, N_BIG)
+            t = time.perf_counter()
+            oracle.sort_keys(a)
+            return time.perf_counter() - t
+        with cf.ThreadPoolExecutor(len(types)) as ex:
+            secs = dict(zip(types, ex.map(leg, types)))
+        cpu["legs_256M"] = {k: {"s": round(v, 2), "Mkeys_s": round(N_BIG / v / 1e6, 3), "cores": 1,
+                                "seed": hex(inputs.seed_for(2, types.index(k), N_BIG))}
+                            for k, v in secs.items()}
+        cpu["legs_256M_note"] = ("one single-threaded oracle sort of each 268,435,456-key input, the four "
+                                 "running at once on four host threads")
+        log(f"cpu 256M legs: {cpu['legs_256M']}")
+    return cpu
+
+
+def comparisons_section(np, inputs, types, host_input):
+    """Sec. 5 of the paper for its mergesort as a CPU program (baseline/):
+    comparisons per key at n = 2,000,000 for random int32 keys, the four input
+    types and the Sec. 2 classes (mean over k = 2^0..2^8), and the regression
+    g(n) = f(n)/n = s log2(n) + t over n = j * 10^6, j = 1..5 (per class, the
+    mean over k at each n).  Runs on a pool of host threads."""
+    import concurrent.futures as cf
+    import baseline
+    classes = ("equal_teeth", "even_teeth", "sharp_teeth", "shuffled_teeth", "distance", "exchange", "limited")
+    ks = [1 << i for i in range(9)]
+
+    def count(job):
+        name, n, k = job
+        if name == "random_int":
+            a = inputs.random_int32(n, inputs.seed_for(7, 0, n))
+        elif name in types:
+            a = host_input(name, n)
+        else:
+            a = inputs.class_int32(name, n, k, inputs.seed_for(6, classes.index(name), k))
+        return job, baseline.sort(a)[1] / n
+
+    jobs = [("random_int", j * 10**6, 0) for j in range(1, 6)]
+    jobs += [(t, N_SMALL, 0) for t in types]
+    jobs += [(c, j * 10**6, k) for c in classes for j in range(1, 6) for k in ks]
+    t0 = time.perf_counter()
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
+    with cf.ThreadPoolExecutor(threads) as ex:
+        got = dict(ex.map(count, jobs))
+    per_n = {}
+    for (name, n, k), g in got.items():
+        per_n.setdefault(name, {}).setdefault(n, []).append(g)
+    out = {"n": N_SMALL, "minrun": baseline.MINRUN, "gallop_after": baseline.GALLOP_AFTER,
+           "per_key_2M": {}, "regression": {}}
+    for name, by_n in per_n.items():
+        gs = {n: float(np.mean(v)) for n, v in by_n.items()}
+        if 2_000_000 in gs:
+            out["per_key_2M"][name] = round(gs[2_000_000], 3)
+        if len(gs) == 5:
+            x = np.log2(np.array(sorted(gs)))
+            y = np.array([gs[n] for n in sorted(gs)])
+            s_, t_ = np.polyfit(x, y, 1)
+            out["regression"][name] = {"s": round(float(s_), 3), "t": round(float(t_), 3)}
+    out["host_s"] = round(time.perf_counter() - t0, 1)
+    log(f"comparisons: {out}")
+    return out
 
 
 def lists_section(torch, inputs, sortrace, dev):
@@ -477,9 +598,8 @@ def classes_section(args, torch, np, inputs, sortrace, dev, stream):
     """The presorted classes of Sec. 2 as in Tables 2-3: n = 2M, k = 2^0..2^8,
     each input sorted by the adaptive plan and by the forced general path
     (tile sort + every merge pass); mean times over k per class.  Two 256M
-    teeth inputs show the pass counts at scale.  k-shuffled teeth is left out
-    (its generator is a sequential shuffle; the GPU treats it as random)."""
-    names = ("equal_teeth", "even_teeth", "sharp_teeth", "distance", "exchange", "limited")
+    teeth inputs show the pass counts at scale."""
+    names = ("equal_teeth", "even_teeth", "sharp_teeth", "shuffled_teeth", "distance", "exchange", "limited")
     ks = [1 << i for i in range(9)]
 
     def time_sort(src, work, reps, force=None):
@@ -605,19 +725,33 @@ def serve_section(args, torch, np, inputs, sortrace, dev):
     closed = run(cfg_batched, np.zeros(R))
     cap = closed["throughput_req_s"]
     plain_closed = run(cfg_plain, np.zeros(R))
+    pcap = plain_closed["throughput_req_s"]
     out = {"requests": R, "sizes": f"log-uniform [{lo}, {hi}]", "mean_keys": int(sizes.mean()),
            "dtypes": "50% float32 N(0,1)+specials, 50% int32 uniform", "hbm_budget_bytes": budget,
            "batched_config": cfg_batched, "capacity_req_s": cap,
-           "capacity_Mkeys_s": closed["Mkeys_s"], "plain_capacity_req_s": plain_closed["throughput_req_s"],
+           "capacity_Mkeys_s": closed["Mkeys_s"], "plain_capacity_req_s": pcap,
+           "plain_capacity_Mkeys_s": plain_closed["Mkeys_s"],
+           "loads_note": "each server at rho x its OWN closed-loop capacity; 'shared' is one absolute "
+                         "rate below both capacities (0.8 x the plain server's) offered to both",
            "loads": {}}
     ea = inputs.unit_double(inputs.stream(inputs.seed_for(5, 3, 0), R))
+    unit_gaps = -np.log(1.0 - ea)   # exponential inter-arrivals of mean 1
+
+    def at(cfg, lam, own_cap):
+        r = run(cfg, np.cumsum(unit_gaps / lam))
+        r["offered_req_s"] = round(lam, 1)
+        r["overloaded"] = bool(lam > own_cap)
+        return r
     for rho in (0.5, 0.8, 0.95):
-        lam = rho * cap
-        arrivals = np.cumsum(-np.log(1.0 - ea) / lam)
-        b = run(cfg_batched, arrivals)
-        p = run(cfg_plain, arrivals)
-        out["loads"][str(rho)] = {"offered_req_s": round(lam, 1), "batched": b, "plain": p}
+        b = at(cfg_batched, rho * cap, cap)
+        p = at(cfg_plain, rho * pcap, pcap)
+        out["loads"][str(rho)] = {"batched": b, "plain": p}
         log(f"serving rho={rho}: batched {b} | plain {p}")
+    lam = 0.8 * min(pcap, cap)
+    b = at(cfg_batched, lam, cap)
+    p = at(cfg_plain, lam, pcap)
+    out["loads"]["shared"] = {"offered_req_s": round(lam, 1), "batched": b, "plain": p}
+    log(f"serving shared load {lam:.0f} req/s: batched {b} | plain {p}")
     # correctness: every request equals the same array sorted alone
     restore()
     with sortrace.Server(budget, **cfg_batched) as srv:

@@ -45,6 +45,7 @@ struct Req {
     void* keys;
     size_t n;
     size_t foot;
+    hipEvent_t ready = nullptr;  // producer's event; the batch's stream waits for it
     double t_arrive, t_admit = -1, t_launch = -1, t_done = -1;
     int batch = -1;
     sr_status status = SR_OK;
@@ -126,10 +127,22 @@ void sr_server::loop() {
                 sl.h_ptrs[q] = r.keys;
                 sl.h_lens[q] = (int64_t)r.n;
             }
+            std::vector<hipEvent_t> waits;
+            for (size_t q : sl.reqs)
+                if (reqs[q].ready) waits.push_back(reqs[q].ready);
             lk.unlock();
-            sr_status s;
+            sr_status s = SR_OK;
             std::string msg;
-            if (sl.reqs.size() == 1) {
+            for (hipEvent_t ev : waits) {
+                if (hipStreamWaitEvent(sl.st, ev, 0) != hipSuccess) {
+                    s = SR_ERR_DEVICE;
+                    msg = std::string("waiting for a request's ready event: ") + hipGetErrorString(hipGetLastError());
+                    break;
+                }
+            }
+            if (s != SR_OK) {
+                // nothing enqueued for this batch; it finishes with the error below
+            } else if (sl.reqs.size() == 1) {
                 s = sr_sort_keys(dt, sl.h_ptrs[0], (size_t)sl.h_lens[0], sl.st);
             } else if (hipMemcpyAsync(sl.d_ptrs, sl.h_ptrs, sizeof(void*) * sl.reqs.size(), hipMemcpyHostToDevice,
                                       sl.st) != hipSuccess ||
@@ -197,8 +210,9 @@ sr_status sr_server_create(const sr_server_config* cfg, sr_server** out) {
             sr_server_destroy(s);
             return SR_ERR_OUT_OF_MEMORY;
         }
-        // size every stream's scratch for the largest batch up front
-        for (sr_dtype dt : {SR_INT32, SR_FLOAT32}) {
+        // size every stream's scratch for the largest batch of every dtype up
+        // front, so the worker loop never allocates
+        for (sr_dtype dt : {SR_INT32, SR_FLOAT32, SR_UINT64}) {
             if (sr_reserve(dt, cfg->max_batch_keys, (size_t)cfg->max_batch_requests, sl.st) != SR_OK) {
                 sr_server_destroy(s);
                 return SR_ERR_OUT_OF_MEMORY;
@@ -215,7 +229,8 @@ sr_status sr_server_create(const sr_server_config* cfg, sr_server** out) {
     return SR_OK;
 }
 
-sr_status sr_server_submit(sr_server* s, sr_dtype dt, void* keys, size_t n, uint64_t tag, double t_arrive) {
+sr_status sr_server_submit(sr_server* s, sr_dtype dt, void* keys, size_t n, uint64_t tag, double t_arrive,
+                           void* ready_event) {
     if (!s || (dt != SR_INT32 && dt != SR_FLOAT32 && dt != SR_UINT64) || (n > 0 && !keys)) return SR_ERR_INVALID_ARGUMENT;
     Req r;
     r.tag = tag;
@@ -224,6 +239,7 @@ sr_status sr_server_submit(sr_server* s, sr_dtype dt, void* keys, size_t n, uint
     r.n = n;
     r.foot = 2 * n * (size_t)es_of(dt);
     r.t_arrive = t_arrive;
+    r.ready = (hipEvent_t)ready_event;
     if (r.foot > s->cfg.hbm_budget_bytes || n > s->cfg.max_batch_keys) return SR_ERR_INVALID_ARGUMENT;
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->arriving.empty() && s->reqs[s->arriving.back()].t_arrive > t_arrive)
