@@ -73,8 +73,6 @@ struct Ctl {
     int dual;                         // OUTLIER beside a run plan (the sample's turning points are rare)
     unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
     unsigned long long run[4];        // RUNS: merge leaves, merge passes, keys reversed, keys in dense pieces
-    unsigned int near_bad;            // GENERAL: some sorted tile overlaps more than its neighbours allow
-    unsigned int pad1;
 };
 
 // Plain relaxed agent-scope accessors (coherent across the XCDs' L2s), for

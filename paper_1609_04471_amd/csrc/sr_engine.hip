@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
     const int valid = (int)((v.n - base) < TS::T ? (v.n - base) : TS::T);
     // the general plan's tiles describe themselves for merge slot 0's NEAR test
     unsigned long long* desc =
-        (tdesc != nullptr && ctl != nullptr && ctl->path == SR_PATH_GENERAL) ? tdesc + 4 * blockIdx.x : nullptr;
+        (tdesc != nullptr && ctl != nullptr && ctl->path == SR_PATH_NEAR) ? tdesc + 4 * blockIdx.x : nullptr;
     TS::run(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
             valid, desc);
 }
@@ -1109,7 +1109,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
 template <class C>
 __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C::S* S1, int64_t n, int M,
                                                    int64_t T, int k, int CH, int64_t* co, const Ctl* ctl,
-                                                   const RunArea* ra, int near = 0) {
+                                                   const RunArea* ra) {
     using S = typename C::S;
     if (ra != nullptr && ctl != nullptr && ctl->path == SR_PATH_RUNS) {
         // RUNS: co-rank of every chunk of the pass inside its leaf group
@@ -1122,8 +1122,7 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
         }
         return;
     }
-    const bool near_on = near != 0 && ctl->force_path != SR_PATH_GENERAL;
-    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k, near_on);
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k);
     if (!v.active) return;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (c * CH >= v.n) return;
@@ -1166,9 +1165,8 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
             }
         }
     }
-    const bool near_on = tdesc != nullptr && ctl->force_path != SR_PATH_GENERAL;
-    if (near_on && k == 0 && ctl->path == SR_PATH_GENERAL) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
-    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k, near_on);
+    if (tdesc != nullptr && k == 0 && ctl->path == SR_PATH_NEAR) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
     const int64_t nch = v.active ? (v.n + MC::CH - 1) / MC::CH : 0;
     if (v.cn > 0 && (int64_t)blockIdx.x >= nch) {
         // workgroups past the merge's chunks copy (the grid has at least T / CH of them)
@@ -1211,9 +1209,8 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
             }
         }
     }
-    const bool near_on = tdesc != nullptr && ctl->force_path != SR_PATH_GENERAL;
-    if (near_on && k == 0 && ctl->path == SR_PATH_GENERAL) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
-    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k, near_on);
+    if (tdesc != nullptr && k == 0 && ctl->path == SR_PATH_NEAR) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
     if (v.cn > 0) copy_part(v.csrc, v.cdst, v.cpsrc, v.cpdst, v.cn, (int64_t)blockIdx.x, (int64_t)gridDim.x);
     if (!v.active) return;
     MP::template run<NT>(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
@@ -1862,7 +1859,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             for (int q = 0; q < 4; ++q) red[q][wave] = acc[q];
         __syncthreads();
     }
-    __shared__ int s_path, s_force, s_dual;
+    __shared__ int s_path, s_force, s_dual, s_force_near;
     __shared__ unsigned long long s_desc, s_asc;
     if (last && tid == 0) {
         unsigned long long tot[4] = {0, 0, 0, 0};
@@ -1908,6 +1905,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                      ? -(runs_like ? SR_PATH_RUNS : SR_PATH_GENERAL) - 10
                      : path;
         s_force = force == SR_PATH_FEW;
+        // forcing GENERAL rules NEAR out; forcing NEAR tries it on any input
+        s_force_near = force == SR_PATH_GENERAL ? -1 : force == SR_PATH_NEAR ? 1 : 0;
         s_dual = path == SR_PATH_OUTLIER && force != SR_PATH_OUTLIER && runs_like;
         s_desc = desc;
         s_asc = asc;
@@ -2024,6 +2023,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                 path = -path - 10;
             }
         }
+        // a general sort is first a NEAR candidate, which merge slot 0 confirms
+        // or turns back into GENERAL (the first merge pass is the same)
+        if ((jobs_ok & 8) != 0 && ((path == SR_PATH_GENERAL && s_force_near >= 0) || s_force_near > 0))
+            path = SR_PATH_NEAR;
         if (tid == 0) {
             ctl->path = path;
             ctl->dual = s_dual;
@@ -2037,7 +2040,6 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             ctl->job_passes = 0;
             ctl->n_kept = 0;
             st_agent(&ctl->bad_join, 0u);
-            st_agent(&ctl->near_bad, 0u);
             ctl->ticket2 = 0;
             unsigned int ep = (ctl->epoch + 1u) & 0xFFFFFFu;
             ctl->epoch = ep == 0u ? 1u : ep;
@@ -2553,7 +2555,6 @@ struct LastCall {
     int es = 0;
     int merge_passes = 0;
     int trivial = 1;
-    bool near = false;    // the NEAR plan was possible
     Ctl* ctl = nullptr;
 };
 
@@ -2914,7 +2915,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         const double pass_us = kPassFloorUs + (double)n * (double)(sizeof(S) + (PAIRS ? 4 : 0)) * 2.0 / 5.5e6;
         const int runs_pmax = M - (int)std::ceil(kRunScanUs / pass_us);
         hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
-                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0), runs_pmax, ftab);
+                           (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0) | (near_ok ? 8 : 0), runs_pmax,
+                           ftab);
         SR_LAUNCH_CHECK("probe");
     }
     if (scan_ok) {
@@ -2976,8 +2978,7 @@ tile_done:
             {
                 ProfScope ps(ls, "partition");
                 hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, ls, keys, skeys,
-                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea,
-                                   near_ok ? 1 : 0);
+                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea);
                 SR_LAUNCH_CHECK("partition");
             }
             ProfScope ps(ls, "merge");
@@ -3016,7 +3017,6 @@ tile_done:
     }
     if (noalloc) return SR_OK;
     lc.trivial = 0;
-    lc.near = near_ok;
     lc.ctl = ctl;
     lc.tile = T;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -3550,6 +3550,12 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             eq = 1.0 + (2.0 + h.job_passes) * m / (double)lc.n;
             break;
         }
+        case SR_PATH_NEAR:
+            // tile sort, two neighbour rounds, and a copy back when the
+            // second round had to write the partner buffer
+            out->merge_passes = 2 + (lc.merge_passes & 1);
+            eq = 1 + out->merge_passes;
+            break;
         case SR_PATH_RUNS: {
             // run scan (n read) + reversal and dense tile sorts + merge tree
             out->run_leaves = (int64_t)h.run[0];
@@ -3558,14 +3564,6 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             break;
         }
         default:
-            if (h.path == SR_PATH_GENERAL && lc.near && h.near_bad == 0 && h.force_path != SR_PATH_GENERAL) {
-                // tile sort, two neighbour rounds, and a copy back when the
-                // second round had to write the partner buffer
-                out->path = SR_PATH_NEAR;
-                out->merge_passes = 2 + (lc.merge_passes & 1);
-                eq = 1 + out->merge_passes;
-                break;
-            }
             out->merge_passes = lc.merge_passes;
             eq = 1 + lc.merge_passes;
             break;
@@ -3597,7 +3595,7 @@ sr_status sr_set_option(const char* name, int64_t value) {
     if (!name) return fail(SR_ERR_INVALID_ARGUMENT, "name is NULL");
     std::lock_guard<std::mutex> lk(g_mu);
     if (std::strcmp(name, "force_path") == 0) {
-        if (value < -1 || value > SR_PATH_FEW) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
+        if (value < -1 || value > SR_PATH_NEAR) return fail(SR_ERR_INVALID_ARGUMENT, "bad force_path");
         g_force_path = (int)value;
         return SR_OK;
     }

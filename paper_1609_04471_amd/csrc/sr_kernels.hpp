@@ -657,7 +657,8 @@ __device__ __forceinline__ void copy_part(const S* src, S* dst, const uint32_t* 
 // at most T/2 keys); (c) at most T/2 keys of tile t are above first(t+1): key
 // T/2-1 of t <= first(t+1).  Then after the rounds (0,1),(2,3),... and
 // (1,2),(3,4),... of T-blocks every block boundary is in order.  A
-// violation anywhere sets near_bad (reset by the probe).
+// violation anywhere turns the plan back into GENERAL: every workgroup of
+// slot 0 merges alike under both names, and slot 1 on reads the final one.
 __device__ __forceinline__ void near_check(Ctl* ctl, const unsigned long long* td, int64_t n, int64_t T) {
     const int64_t ntiles = (n + T - 1) / T;
     const int64_t H = T / 2;
@@ -673,8 +674,7 @@ __device__ __forceinline__ void near_check(Ctl* ctl, const unsigned long long* t
             if (d[2] > e[0]) bad = true;
         }
     }
-    if (__builtin_amdgcn_ballot_w64(bad) != 0ull && __lane_id() == 0 && ld_agent(&ctl->near_bad) == 0u)
-        atomicOr(&ctl->near_bad, 1u);
+    if (__builtin_amdgcn_ballot_w64(bad) != 0ull && __lane_id() == 0) ctl->path = 3 /* SR_PATH_GENERAL */;
 }
 
 // ============================================================ job views
@@ -702,24 +702,22 @@ struct PassView {
     int64_t cn;
 };
 
-// NEAR (on the general plan, decided by merge slot 0 from the tile
-// descriptors): slot 1 merges the T-blocks (1,2), (3,4), ... of slot 0's
-// output -- the array viewed from offset T, in groups of two blocks -- and
-// copies block 0; it writes U when slot 0 wrote S1 (M even), else S1, and then
-// slot 2 copies S1 back to U.  Later slots do nothing.
-__device__ __forceinline__ bool near_taken(const Ctl* ctl, bool near_on) {
-    return near_on && ld_agent(&ctl->near_bad) == 0u;
-}
+// NEAR (the general plan's candidate, confirmed by merge slot 0 from the tile
+// descriptors, which turns it back into GENERAL otherwise): slot 0 is the
+// general plan's first pass; slot 1 merges the T-blocks (1,2), (3,4), ... of
+// slot 0's output -- the array viewed from offset T, in groups of two blocks --
+// and copies block 0; it writes U when slot 0 wrote S1 (M even), else S1, and
+// then slot 2 copies S1 back to U.  Later slots do nothing.
 
 template <class S>
 __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
-                                                     int64_t n, int M, int64_t T, int k, bool near_on = false) {
+                                                     int64_t n, int M, int64_t T, int k) {
     PassView<S> v{};
     v.active = false;
     v.split = -1;
     v.cn = 0;
     const int path = ctl->path;
-    if (path == 3 /* SR_PATH_GENERAL */ && k >= 1 && near_taken(ctl, near_on)) {
+    if (path == 6 /* SR_PATH_NEAR */ && k >= 1) {
         const bool to_s1 = (M & 1) == 0;  // slot 0 wrote S1
         S* X = to_s1 ? S1 : U;
         S* Y = to_s1 ? U : S1;
@@ -747,7 +745,7 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
         }
         return v;
     }
-    if (path == 3 /* SR_PATH_GENERAL */) {
+    if (path == 3 /* SR_PATH_GENERAL */ || path == 6 /* SR_PATH_NEAR: slot 0 */) {
         const int from = (M - k) & 1;
         v.src = from ? S1 : U;
         v.dst = from ? U : S1;
@@ -795,7 +793,7 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         return v;
     }
     const int path = ctl->path;
-    if (path == 3 /* SR_PATH_GENERAL */) {
+    if (path == 3 /* SR_PATH_GENERAL */ || path == 6 /* SR_PATH_NEAR */) {
         v.src = U;
         v.dst = (M & 1) ? S1 : U;
         v.psrc = PU;
