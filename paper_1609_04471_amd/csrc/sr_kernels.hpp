@@ -780,35 +780,44 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
 template <class S>
 __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
                                                     int64_t n, int M) {
-    PassView<S> v{};
-    v.active = false;
-    v.split = -1;
-    if (ctl == nullptr) {  // single tile: in place
-        v.src = U;
-        v.dst = U;
-        v.psrc = PU;
-        v.pdst = PU;
-        v.n = n;
-        v.active = true;
-        return v;
-    }
-    const int path = ctl->path;
-    if (path == 3 /* SR_PATH_GENERAL */ || path == 6 /* SR_PATH_NEAR */) {
-        v.src = U;
-        v.dst = (M & 1) ? S1 : U;
-        v.psrc = PU;
-        v.pdst = (M & 1) ? PS1 : PU;
-        v.n = n;
-        v.active = true;
-    } else if (path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW */) {
-        const int64_t m = (int64_t)ctl->m;
-        const int P = ctl->job_passes;
+    // Every field is chosen as a scalar and the view built once at the end:
+    // a view assembled field by field on different branches was kept in
+    // scratch memory (a per-lane stack slot written on every launch).
+    S* src = U;  // single tile (no plan): in place
+    S* dst = U;
+    const uint32_t* psrc = PU;
+    uint32_t* pdst = PU;
+    int64_t len = n;
+    bool active = true;
+    if (ctl != nullptr) {
+        const int path = ctl->path;
+        const bool general = path == 3 /* SR_PATH_GENERAL */ || path == 6 /* SR_PATH_NEAR */;
+        const bool job = path == 2 /* SR_PATH_OUTLIER */ || path == 5 /* SR_PATH_FEW */;
+        const int64_t m = job ? (int64_t)ctl->m : 0;
+        const int P = job ? ctl->job_passes : 0;
         S* X0 = S1 + (n - m);
-        v.src = X0;
-        v.dst = (P & 1) ? U : X0;
-        v.n = m;
-        v.active = true;
+        const bool odd = (M & 1) != 0;
+        src = job ? X0 : U;
+        dst = job ? ((P & 1) ? U : X0) : (odd ? S1 : U);
+        psrc = job ? nullptr : PU;
+        pdst = job ? nullptr : (odd ? PS1 : PU);
+        len = job ? m : n;
+        active = general || job;
     }
+    PassView<S> v;
+    v.src = src;
+    v.dst = dst;
+    v.psrc = psrc;
+    v.pdst = pdst;
+    v.n = len;
+    v.width = 0;
+    v.split = -1;
+    v.active = active;
+    v.csrc = nullptr;
+    v.cdst = nullptr;
+    v.cpsrc = nullptr;
+    v.cpdst = nullptr;
+    v.cn = 0;
     return v;
 }
 
