@@ -92,7 +92,9 @@ typedef struct {
                               keys not equal to any sampled value */
     double bytes_moved;    /* algorithmic HBM bytes: unrounded passes x 2 x n x element bytes */
     int64_t run_leaves;    /* RUNS path: sorted leaves left after the in-order joins */
-    int32_t merge_passes;  /* merge passes of the chosen path (RUNS: over its leaves) */
+    int32_t merge_passes;  /* merge passes of the chosen path (RUNS: over its leaves;
+                              GENERAL with fan-in four: passes over the array, a
+                              four-way pass counting once) */
     int32_t pad;
 } sr_stats;
 
@@ -366,6 +368,14 @@ const char *sr_last_error_message(void);
  *                 -1 = auto (built-in: on for keys-only sorts from 256 MiB
  *                 of keys, for uint64 pairs from 128 MiB of keys, never for
  *                 32-bit pairs).
+ *   "fan_in"      merge fan-in of keys-only general sorts that use the
+ *                 partition shape: 4 = four-way passes (each group of four
+ *                 neighbouring runs is cut at every 2048th key of each run --
+ *                 every 1024th for 64-bit keys -- and merged as two levels in
+ *                 LDS, so two levels of the merge tree cost one pass over the
+ *                 array; a sort that takes this schedule does not try the
+ *                 NEAR plan), 2 = two-way, 0 = auto (tuning table, then
+ *                 built-in).  Pairs always merge two-way.
  * Returns SR_ERR_INVALID_ARGUMENT for an unknown name or value.
  */
 sr_status sr_set_option(const char *name, int64_t value);
@@ -391,7 +401,10 @@ typedef struct {
                               rows are looked up by the total key count and use only
                               tile_variant and merge_items (32-bit keys, keys only;
                               partition and nontemporal must be unset there) */
-    int32_t pad;           /* 0 */
+    int32_t fan_in;        /* merge fan-in of plain keys-only sorts with the partition shape:
+                              4 = four-way passes (each merges two levels of the merge
+                              tree in one read and one write of the array), 2 = two-way;
+                              0 = unset.  Must be 0 or 2 for pairs and segmented rows. */
 } sr_tune_entry;
 
 /* Replaces the process-wide tuning table with `count` rows copied from host

@@ -1019,7 +1019,8 @@ __device__ __forceinline__ void few_place(typename C::S* U, const typename C::S*
 template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                   uint32_t* PS1, int64_t n, int M, const Ctl* ctl,
-                                                  const RunTile* rdesc, unsigned long long* tdesc = nullptr) {
+                                                  const RunTile* rdesc, unsigned long long* tdesc = nullptr,
+                                                  int fan4 = 0) {
     using TS = TileSort<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename TS::Smem sm;
@@ -1092,7 +1093,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
         }
         return;
     }
-    const PassView<S> v = resolve_tile(ctl, U, S1, PU, PS1, n, M);
+    const PassView<S> v = resolve_tile(ctl, U, S1, PU, PS1, n, M, fan4 != 0);
     if (!v.active) return;
     const int64_t base = (int64_t)blockIdx.x * TS::T;
     if (base >= v.n) return;
@@ -1109,7 +1110,7 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
 template <class C>
 __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C::S* S1, int64_t n, int M,
                                                    int64_t T, int k, int CH, int64_t* co, const Ctl* ctl,
-                                                   const RunArea* ra) {
+                                                   const RunArea* ra, int fan4 = 0) {
     using S = typename C::S;
     if (ra != nullptr && ctl != nullptr && ctl->path == SR_PATH_RUNS) {
         // RUNS: co-rank of every chunk of the pass inside its leaf group
@@ -1122,8 +1123,8 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
         }
         return;
     }
-    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k);
-    if (!v.active) return;
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k, fan4 != 0);
+    if (!v.active || v.fan == 4) return;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (c * CH >= v.n) return;
     const int64_t out0 = c * CH;
@@ -1187,7 +1188,8 @@ template <class C, int WG, int IT, bool PAIRS, bool NT = false>
 __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename C::S* S1, uint32_t* PU,
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
                                                       const int64_t* co, const Ctl* ctl, const RunArea* ra,
-                                                      const FewTable* ft, const unsigned long long* tdesc = nullptr) {
+                                                      const FewTable* ft, const unsigned long long* tdesc = nullptr,
+                                                      int fan4 = 0) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
     using MC = typename MP::MC;
     using S = typename C::S;
@@ -1210,10 +1212,35 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         }
     }
     if (tdesc != nullptr && k == 0 && ctl->path == SR_PATH_NEAR) near_check(const_cast<Ctl*>(ctl), tdesc, n, T);
-    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k);
+    const PassView<S> v = resolve_merge(ctl, U, S1, PU, PS1, n, M, T, k, fan4 != 0);
     if (v.cn > 0) copy_part(v.csrc, v.cdst, v.cpsrc, v.cpdst, v.cn, (int64_t)blockIdx.x, (int64_t)gridDim.x);
-    if (!v.active) return;
+    if (!v.active || v.fan == 4) return;
     MP::template run<NT>(sm.p, v.src, v.dst, v.psrc, v.pdst, v.n, v.width, v.split, co);
+}
+
+// Four-way pass at merge slot k (general plan, fan-in four): the cut of
+// every sample, then one workgroup per chunk.  Both return at once unless
+// slot k is a four-way pass of the plan.
+template <class C>
+__global__ __launch_bounds__(256) void k_part4(typename C::S* U, typename C::S* S1, int64_t n, int M, int64_t T,
+                                               int k, uint4* splits, const Ctl* ctl) {
+    using S = typename C::S;
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k, true);
+    if (!v.active || v.fan != 4) return;
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= Merge4<C>::sample_slots(n, v.width)) return;
+    Merge4<C>::sample(v.src, n, v.width, s, splits);
+}
+
+template <class C, bool NT>
+__global__ __launch_bounds__(256) void k_merge4(typename C::S* U, typename C::S* S1, int64_t n, int M, int64_t T,
+                                                int k, const uint4* splits, const Ctl* ctl) {
+    using S = typename C::S;
+    static_assert(Merge4<C>::WG == 256, "launch shape");
+    __shared__ typename Merge4<C>::Smem sm;
+    const PassView<S> v = resolve_merge(ctl, U, S1, (uint32_t*)nullptr, (uint32_t*)nullptr, n, M, T, k, true);
+    if (!v.active || v.fan != 4) return;
+    Merge4<C>::template chunk<NT>(sm, v.src, v.dst, n, v.width, (int64_t)blockIdx.x, splits);
 }
 
 // --------------------------------------------------------------- outliers
@@ -2399,6 +2426,7 @@ int64_t g_partition_min_n = -1;  // separate Merge Path partition launch from th
 int g_tile_variant = -1;         // 0: 512 x 16, 1: 1024 x 8 (32-bit keys only)
 int g_merge_items = 0;           // fused merge: outputs per thread, 8 or 16 (32-bit keys only)
 int g_nontemporal = -1;          // persistent merge: nontemporal window loads and stores
+int g_fan_in = 0;                // merge fan-in of general sorts: 2, 4, 0 = auto (table, then built-in)
 std::vector<sr_tune_entry> g_tune;  // sorted by (dtype, pairs, min_n)
 uint64_t g_tune_version = 0;        // bumped by every sr_tune_set (captured graphs key on it)
 
@@ -2406,6 +2434,7 @@ uint64_t g_tune_version = 0;        // bumped by every sr_tune_set (captured gra
 constexpr int64_t kPartitionMinN = (int64_t)1 << 23;
 constexpr int64_t kMerge16MinN = (int64_t)1 << 21;     // fused merge: 16 outputs per thread from here
 constexpr size_t kNontemporalBytes = (size_t)1 << 28;  // of keys: two such arrays exceed the MALL
+constexpr int64_t kFan4MinN = (int64_t)1 << 62;         // four-way passes from here (set from measurements)
 constexpr int64_t kTuneMaxRows = 1024;
 
 // sr_dtype of a codec
@@ -2423,6 +2452,7 @@ struct LaunchShape {
     int tile_variant;  // 0: TWG x TIT, 1: 1024 x 8 (32-bit keys)
     int merge_items;   // fused merge outputs per thread (32-bit keys)
     bool nt;           // nontemporal persistent merge
+    int fan_in;        // 2, or 4: four-way passes for keys-only general sorts (partition shape only)
 };
 
 // Explicit options first, then the table row of (dt, pairs) with the largest
@@ -2445,6 +2475,10 @@ LaunchShape resolve_shape(int dt, bool pairs, int64_t n, size_t key_bytes) {
     else if (row && row->nontemporal >= 0) sh.nt = row->nontemporal != 0;
     else if (!pairs) sh.nt = (size_t)n * key_bytes >= kNontemporalBytes;
     else sh.nt = key_bytes == 8 && (size_t)n * key_bytes >= kNontemporalBytes / 2;  // not for 32-bit pairs
+    if (g_fan_in > 0) sh.fan_in = g_fan_in;
+    else if (row && row->fan_in > 0) sh.fan_in = row->fan_in;
+    else sh.fan_in = !pairs && n >= kFan4MinN ? 4 : 2;
+    if (pairs) sh.fan_in = 2;
     return sh;
 }
 
@@ -2555,6 +2589,7 @@ struct LastCall {
     int es = 0;
     int merge_passes = 0;
     int trivial = 1;
+    bool fan4 = false;  // general passes were four-way
     Ctl* ctl = nullptr;
 };
 
@@ -2850,8 +2885,21 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     const bool few_ok = !PAIRS && g_few_enabled;
     const bool scan_ok = outlier_ok || runs_ok || few_ok;
     const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
-    // co-ranks of a merge pass; a RUNS pass has up to one extra chunk per leaf group
-    const size_t co_bytes = round_up((size_t)(nchunks + 2 + kRunMaxLeaves) * 8, 256);
+    LaunchShape sh;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sh = resolve_shape(DtypeOf<C>::value, PAIRS, n, sizeof(S));
+    }
+    const bool use_partition = sh.partition;
+    // four-way general passes: keys only, with the partition launch shape,
+    // at least one pair of levels, cuts held in 32 bits
+    const bool fan4 = !PAIRS && use_partition && sh.fan_in == 4 && M >= 2 && n <= (int64_t)UINT32_MAX;
+    // co-ranks of a merge pass; a RUNS pass has up to one extra chunk per leaf
+    // group; a four-way pass keeps the cut of every sample (16 bytes) there
+    const size_t co_bytes =
+        round_up(std::max((size_t)(nchunks + 2 + kRunMaxLeaves) * 8,
+                          fan4 ? (size_t)(Merge4<C>::chunks(n, (int64_t)T) + 8) * 16 : (size_t)0),
+                 256);
     const size_t kbytes = round_up((size_t)n * sizeof(S), 256);
     // tile summaries (ver_slot layout: whole verify rounds) and tile prefixes
     const size_t cls_arr = round_up((size_t)round_up((size_t)ncls, (size_t)kVerRound) * 8, 256);
@@ -2865,7 +2913,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     bool near_ok;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        near_ok = g_near_enabled && M >= 3;
+        near_ok = g_near_enabled && M >= 3 && !fan4;
     }
     const size_t tdesc_bytes = near_ok ? round_up((size_t)ntiles * 32, 256) : 0;
     const size_t data_need = co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0);
@@ -2888,12 +2936,6 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     int64_t* co = reinterpret_cast<int64_t*>(wd);
     S* skeys = reinterpret_cast<S*>(wd + co_bytes);
     uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes) : nullptr;
-    LaunchShape sh;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        sh = resolve_shape(DtypeOf<C>::value, PAIRS, n, sizeof(S));
-    }
-    const bool use_partition = sh.partition;
     const bool merge8 = sizeof(S) == 4 && !PAIRS && TN::MIT == 16 && sh.merge_items == 8;
     const int64_t merge_ch = use_partition ? CH : (merge8 ? (int64_t)TN::MWG * 8 : CH);
     RunTile* rdesc = nullptr;
@@ -2956,13 +2998,15 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         if constexpr (sizeof(S) == 4 && !PAIRS && TN::TWG * TN::TIT == 1024 * 8) {
             if (sh.tile_variant == 1) {
                 hipLaunchKernelGGL((k_tile_sort<C, 1024, 8, PAIRS>), dim3((unsigned)ntiles), dim3(1024), 0, ls, keys,
-                                   skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc);
+                                   skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc,
+                                   fan4 ? 1 : 0);
                 SR_LAUNCH_CHECK("tile_sort");
                 goto tile_done;
             }
         }
         hipLaunchKernelGGL((k_tile_sort<C, TN::TWG, TN::TIT, PAIRS>), dim3((unsigned)ntiles), dim3(TN::TWG), 0, ls,
-                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc);
+                           keys, skeys, pay, spay, n, M, (const Ctl*)ctl, (const RunTile*)rdesc, tdesc,
+                           fan4 ? 1 : 0);
         SR_LAUNCH_CHECK("tile_sort");
     }
 tile_done:
@@ -2978,17 +3022,39 @@ tile_done:
             {
                 ProfScope ps(ls, "partition");
                 hipLaunchKernelGGL(k_partition<C>, dim3((unsigned)cdiv(nchunks, 256)), dim3(256), 0, ls, keys, skeys,
-                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea);
+                                   n, M, (int64_t)T, k, CH, co, (const Ctl*)ctl, (const RunArea*)rarea,
+                                   fan4 ? 1 : 0);
                 SR_LAUNCH_CHECK("partition");
             }
-            ProfScope ps(ls, "merge");
-            auto kern = sh.nt ? k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, true>
-                           : k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, false>;
-            const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
-            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
-                               (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
-                               (const FewTable*)ftab, (const unsigned long long*)tdesc);
-            SR_LAUNCH_CHECK("merge");
+            // a general sort's four-way pass over levels k and k+1 (the two-way
+            // launches of the slot then return at once; the other plans use
+            // them and these return)
+            const bool four = fan4 && (k & 1) == 0 && k + 1 < M;
+            const int64_t nc4 = four ? Merge4<C>::chunks(n, (int64_t)T << k) : 0;
+            if (four) {
+                ProfScope ps(ls, "part4");
+                const int64_t ns4 = Merge4<C>::sample_slots(n, (int64_t)T << k);
+                hipLaunchKernelGGL(k_part4<C>, dim3((unsigned)cdiv(ns4, 256)), dim3(256), 0, ls, keys, skeys, n, M,
+                                   (int64_t)T, k, reinterpret_cast<uint4*>(co), (const Ctl*)ctl);
+                SR_LAUNCH_CHECK("part4");
+            }
+            {
+                ProfScope ps(ls, "merge");
+                auto kern = sh.nt ? k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, true>
+                                  : k_merge_persist<C, TN::MWG, TN::MIT, PAIRS, false>;
+                const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
+                hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
+                                   (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
+                                   (const FewTable*)ftab, (const unsigned long long*)tdesc, fan4 ? 1 : 0);
+                SR_LAUNCH_CHECK("merge");
+            }
+            if (four) {
+                ProfScope ps(ls, "merge4");
+                auto kern4 = sh.nt ? k_merge4<C, true> : k_merge4<C, false>;
+                hipLaunchKernelGGL(kern4, dim3((unsigned)nc4), dim3(256), 0, ls, keys, skeys, n, M, (int64_t)T, k,
+                                   reinterpret_cast<const uint4*>(co), (const Ctl*)ctl);
+                SR_LAUNCH_CHECK("merge4");
+            }
         } else {
             ProfScope ps(ls, "merge");
             // a RUNS pass k cuts each of its <= kRunMaxLeaves / 2^(k+1) groups
@@ -3017,6 +3083,7 @@ tile_done:
     }
     if (noalloc) return SR_OK;
     lc.trivial = 0;
+    lc.fan4 = fan4;
     lc.ctl = ctl;
     lc.tile = T;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -3111,7 +3178,7 @@ struct GraphKey {
     const void *keys, *pay, *off;
     int64_t n, nseg;
     hipStream_t st;
-    int64_t opts[10];
+    int64_t opts[11];
     unsigned long long gen;
     bool operator<(const GraphKey& o) const {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
@@ -3167,6 +3234,7 @@ sr_status run_maybe_graph(int kind, int dt, const void* keys, const void* pay, c
         key.opts[7] = g_few_enabled;
         key.opts[8] = (int64_t)g_tune_version;
         key.opts[9] = g_near_enabled;
+        key.opts[10] = g_fan_in;
         auto it = g_ws.find({key.dev, st});
         key.gen = it != g_ws.end() && it->second ? it->second->generation : 0;
     }
@@ -3564,8 +3632,9 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             break;
         }
         default:
-            out->merge_passes = lc.merge_passes;
-            eq = 1 + lc.merge_passes;
+            // four-way passes merge two levels each (the last alone when odd)
+            out->merge_passes = lc.fan4 ? lc.merge_passes / 2 + (lc.merge_passes & 1) : lc.merge_passes;
+            eq = 1 + out->merge_passes;
             break;
         }
         out->passes = (int32_t)std::ceil(eq - 1e-9);
@@ -3630,6 +3699,11 @@ sr_status sr_set_option(const char* name, int64_t value) {
         g_nontemporal = (int)value;
         return SR_OK;
     }
+    if (std::strcmp(name, "fan_in") == 0) {
+        if (value != 0 && value != 2 && value != 4) return fail(SR_ERR_INVALID_ARGUMENT, "fan_in is 0, 2 or 4");
+        g_fan_in = (int)value;
+        return SR_OK;
+    }
     if (std::strcmp(name, "outlier_path") == 0) {
         if (value != 0 && value != 1) return fail(SR_ERR_INVALID_ARGUMENT, "outlier_path is 0 or 1");
         g_outlier_enabled = value != 0;
@@ -3679,7 +3753,10 @@ sr_status sr_tune_set(const sr_tune_entry* entries, int64_t count) {
         if (e.segmented != 0 && e.segmented != 1) return fail(SR_ERR_INVALID_ARGUMENT, at + "segmented is 0 or 1");
         if (e.segmented && (e.partition != -1 || e.nontemporal != -1))
             return fail(SR_ERR_INVALID_ARGUMENT, at + "segmented rows leave partition and nontemporal unset");
-        if (e.pad != 0) return fail(SR_ERR_INVALID_ARGUMENT, at + "pad is 0");
+        if (e.fan_in != 0 && e.fan_in != 2 && e.fan_in != 4)
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "fan_in is 0, 2 or 4");
+        if ((e.segmented || e.pairs) && e.fan_in == 4)
+            return fail(SR_ERR_INVALID_ARGUMENT, at + "fan_in 4 is for plain keys-only sorts");
     }
     auto before = [](const sr_tune_entry& a, const sr_tune_entry& b) {
         if (a.dtype != b.dtype) return a.dtype < b.dtype;

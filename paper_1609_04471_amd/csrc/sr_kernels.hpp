@@ -626,6 +626,266 @@ struct MergePersistent {
     }
 };
 
+// ============================================================ four-way merge
+// A pass of fan-in four (keys only): each group of four neighbouring runs
+// R0..R3 of width w (clipped to n) becomes one sorted run of 4w, so two
+// levels of the merge tree cost one read and one write of the array (the
+// rounds of pairwise merging of Sec. 3 (e1), taken two at a time).
+// Partition: run q is sampled every D keys from offset q*D/4 (staggered, so
+// that runs of alike values do not put their samples side by side, which
+// would leave most chunks nearly empty and a few full).  A sample x = R_r[o]
+// cuts the group where x stands in the merge order (key, then run): the keys
+// of R_q before it are those <= x for q < r and those < x for q > r, and its
+// place among the group's cuts follows from those counts (the samples of R_q
+// before x are those at offsets below the count).  Cut 0 is the group start.
+// Between two consecutive cuts each run has fewer than D keys, so a chunk
+// holds at most 4D keys.  One workgroup per chunk stages its four ranges in
+// LDS, merges R0 with R1 and R2 with R3, then the two results, and writes the
+// chunk at its rank.
+template <class C>
+struct Merge4 {
+    using S = typename C::S;
+    using U = typename C::U;
+    static constexpr int WG = 256;
+    static constexpr int D = sizeof(S) == 4 ? 2048 : 1024;  // sample stride
+    static constexpr int CAP = 4 * D;                         // keys of a chunk at most
+    static constexpr int ITM = CAP / WG;                      // outputs per thread at most
+    struct Smem {
+        U k[CAP];
+    };
+
+    static __host__ __device__ __forceinline__ int64_t run_len(int64_t n, int64_t gs, int64_t w, int q) {
+        const int64_t a = n - gs - (int64_t)q * w;
+        return a <= 0 ? 0 : (a < w ? a : w);
+    }
+    // first sampled offset of run q, and the samples of a run of l keys
+    static __host__ __device__ __forceinline__ int64_t phase(int q) { return (int64_t)q * (D / 4); }
+    static __host__ __device__ __forceinline__ int64_t nsamp(int64_t l, int q) {
+        return l <= phase(q) ? 0 : (l - phase(q) + D - 1) / D;
+    }
+    // samples of run q at offsets below c
+    static __device__ __forceinline__ int64_t below(int64_t c, int q) {
+        return c <= phase(q) ? 0 : (c - phase(q) + D - 1) / D;
+    }
+    // cut slots of a full group (its samples and cut 0)
+    static __host__ __device__ __forceinline__ int64_t per_group(int64_t w) { return 4 * (w / D) + 1; }
+
+    // Chunks (= cut slots) of the pass over n keys in runs of w.
+    static __host__ __device__ __forceinline__ int64_t chunks(int64_t n, int64_t w) {
+        if (n <= 0) return 0;
+        const int64_t G = (n + 4 * w - 1) / (4 * w);
+        const int64_t gs = (G - 1) * 4 * w;
+        int64_t last = 1;
+        for (int q = 0; q < 4; ++q) last += nsamp(run_len(n, gs, w, q), q);
+        return (G - 1) * per_group(w) + last;
+    }
+    // Sample threads of the pass: 4 w / D per group, a run after another.
+    static __host__ __device__ __forceinline__ int64_t sample_slots(int64_t n, int64_t w) {
+        return (n + 4 * w - 1) / (4 * w) * (4 * (w / D));
+    }
+
+    // Sample thread s: the cut of its sample into splits[group base + place].
+    static __device__ __forceinline__ void sample(const S* src, int64_t n, int64_t w, int64_t s, uint4* splits) {
+        const int64_t per_run = w / D;
+        const int64_t g = s / (4 * per_run);
+        const int64_t l = s - g * 4 * per_run;
+        const int r = (int)(l / per_run);
+        const int64_t k = l - (int64_t)r * per_run;
+        const int64_t gs = g * 4 * w;
+        const int64_t off = phase(r) + k * D;
+        int64_t lo[4], hi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lo[q] = 0;
+            hi[q] = q == r ? 0 : run_len(n, gs, w, q);
+        }
+        if (off >= run_len(n, gs, w, r)) return;
+        const U x = C::enc(src[gs + (int64_t)r * w + off]);
+        // the three searches advance together, their loads in flight at once
+        for (int step = 0; step < 40; ++step) {
+            U y[4];
+            bool act[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                act[q] = lo[q] < hi[q];
+                const int64_t mid = (lo[q] + hi[q]) >> 1;
+                y[q] = act[q] ? C::enc(src[gs + (int64_t)q * w + mid]) : (U)0;
+            }
+            if (!(act[0] || act[1] || act[2] || act[3])) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (act[q]) {
+                    const int64_t mid = (lo[q] + hi[q]) >> 1;
+                    const bool before = q < r ? y[q] <= x : y[q] < x;
+                    if (before) lo[q] = mid + 1;
+                    else hi[q] = mid;
+                }
+            }
+        }
+        int64_t c[4];
+        int64_t pos = 1 + k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = q == r ? off : lo[q];
+            if (q != r) pos += below(c[q], q);
+        }
+        splits[g * per_group(w) + pos] =
+            make_uint4((unsigned)c[0], (unsigned)c[1], (unsigned)c[2], (unsigned)c[3]);
+    }
+
+    // co-rank of diagonal d between k[a0, a0 + na) and k[b0, b0 + nb) in LDS
+    static __device__ __forceinline__ int corank(const U* k, int a0, int na, int b0, int nb, int d) {
+        int lo = d > nb ? d - nb : 0;
+        int hi = d < na ? d : na;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (k[a0 + mid] <= k[b0 + d - 1 - mid]) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    }
+
+    // Merge cursor over A = k[.., ea) and B = k[.., eb); an exhausted run reads
+    // as the largest code (taking it for an equal key writes the same bits).
+    struct Cur {
+        int pa, ea, pb, eb;
+        U a, b;
+    };
+    static __device__ __forceinline__ Cur cursor(const U* k, int pa, int ea, int pb, int eb) {
+        constexpr U kMax = ~(U)0;
+        Cur c;
+        c.pa = pa;
+        c.ea = ea;
+        c.pb = pb;
+        c.eb = eb;
+        c.a = pa < ea ? k[pa] : kMax;
+        c.b = pb < eb ? k[pb] : kMax;
+        return c;
+    }
+    static __device__ __forceinline__ U next(const U* k, Cur& c) {
+        constexpr U kMax = ~(U)0;
+        const bool ta = c.a <= c.b;
+        const U out = ta ? c.a : c.b;
+        c.pa += ta ? 1 : 0;
+        c.pb += ta ? 0 : 1;
+        const int nx = ta ? c.pa : c.pb;
+        const U kn = nx < (ta ? c.ea : c.eb) ? k[nx] : kMax;
+        c.a = ta ? kn : c.a;
+        c.b = ta ? c.b : kn;
+        return out;
+    }
+
+    // Chunk c of the pass (one workgroup of WG threads).
+    template <bool NT>
+    static __device__ __forceinline__ void chunk(Smem& sm, const S* src, S* dst, int64_t n, int64_t w, int64_t c,
+                                                 const uint4* splits) {
+        const int tid = threadIdx.x;
+        const int64_t per = per_group(w);
+        const int64_t g = c / per;
+        const int64_t t = c - g * per;
+        const int64_t gs = g * 4 * w;
+        int64_t len[4];
+        int64_t ns = 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            len[q] = run_len(n, gs, w, q);
+            ns += nsamp(len[q], q);
+        }
+        if (t >= ns) return;
+        const uint4 a = t == 0 ? make_uint4(0u, 0u, 0u, 0u) : splits[c];
+        const uint4 e = t + 1 < ns ? splits[c + 1]
+                                   : make_uint4((unsigned)len[0], (unsigned)len[1], (unsigned)len[2], (unsigned)len[3]);
+        const int64_t st[4] = {a.x, a.y, a.z, a.w};
+        const int64_t en[4] = {e.x, e.y, e.z, e.w};
+        // a cut out of order or past its run would be a partition error:
+        // the chunk is then left unwritten rather than read out of bounds
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (st[q] > en[q] || en[q] > len[q]) return;
+        const int o1 = (int)(en[0] - st[0]);
+        const int o2 = o1 + (int)(en[1] - st[1]);
+        const int o3 = o2 + (int)(en[2] - st[2]);
+        const int cnt = o3 + (int)(en[3] - st[3]);
+        if (cnt > CAP) return;
+        const int64_t out0 = gs + st[0] + st[1] + st[2] + st[3];
+        // where LDS position i reads from: run q's range, chosen by selects
+        // (a local array indexed at run time would live in scratch)
+        const S* r0 = src + gs + st[0];
+        const S* r1 = src + gs + w + st[1] - o1;
+        const S* r2 = src + gs + 2 * w + st[2] - o2;
+        const S* r3 = src + gs + 3 * w + st[3] - o3;
+        {
+            // loads in batches of 8 per thread, all of a batch in flight before
+            // the first is used: no branch among them (a lane past the chunk
+            // rereads the chunk's last key)
+            constexpr int BJ = 8;
+            const int nj = (cnt + WG - 1) / WG;
+            for (int j0 = 0; j0 < nj; j0 += BJ) {
+                S x[BJ];
+#pragma unroll
+                for (int j = 0; j < BJ; ++j) {
+                    const int i0 = tid + (j0 + j) * WG;
+                    const int i = i0 < cnt ? i0 : cnt - 1;
+                    const S* p = (i < o1 ? r0 : i < o2 ? r1 : i < o3 ? r2 : r3) + i;
+                    if constexpr (NT) x[j] = __builtin_nontemporal_load(p);
+                    else x[j] = *p;
+                }
+#pragma unroll
+                for (int j = 0; j < BJ; ++j) {
+                    const int i = tid + (j0 + j) * WG;
+                    if (i < cnt) sm.k[i] = C::enc(x[j]);
+                }
+            }
+        }
+        __syncthreads();
+        const int it = (cnt + WG - 1) / WG;
+        const int p0 = tid * it;
+        U v[ITM];
+        // level 1: [0, o2) merges R0's range with R1's, [o2, cnt) R2's with R3's
+        {
+            const int d01 = p0 < o2 ? p0 : o2;
+            const int d23 = p0 > o2 ? (p0 < cnt ? p0 - o2 : cnt - o2) : 0;
+            const int i01 = corank(sm.k, 0, o1, o1, o2 - o1, d01);
+            const int i23 = corank(sm.k, o2, o3 - o2, o3, cnt - o3, d23);
+            Cur c01 = cursor(sm.k, i01, o1, o1 + (d01 - i01), o2);
+            Cur c23 = cursor(sm.k, o2 + i23, o3, o3 + (d23 - i23), cnt);
+#pragma unroll
+            for (int r = 0; r < ITM; ++r) {
+                if (r < it) {
+                    const int p = p0 + r;
+                    if (p < o2) v[r] = next(sm.k, c01);
+                    else if (p < cnt) v[r] = next(sm.k, c23);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITM; ++r)
+            if (r < it && p0 + r < cnt) sm.k[p0 + r] = v[r];
+        __syncthreads();
+        // level 2: k[0, o2) with k[o2, cnt)
+        {
+            const int d = p0 < cnt ? p0 : cnt;
+            const int i = corank(sm.k, 0, o2, o2, cnt - o2, d);
+            Cur cc = cursor(sm.k, i, o2, o2 + (d - i), cnt);
+#pragma unroll
+            for (int r = 0; r < ITM; ++r)
+                if (r < it && p0 + r < cnt) v[r] = next(sm.k, cc);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITM; ++r)
+            if (r < it && p0 + r < cnt) sm.k[p0 + r] = v[r];
+        __syncthreads();
+        S* out = dst + out0;
+        for (int i = tid; i < cnt; i += WG) {
+            const S y = C::dec(sm.k[i]);
+            if constexpr (NT) __builtin_nontemporal_store(y, out + i);
+            else out[i] = y;
+        }
+    }
+};
+
 // ============================================================ NEAR plan
 // Part `part` of `parts` of a copy of cn keys (and payloads when psrc is
 // set): 16-byte vectors where both sides are aligned, else elements.
@@ -700,6 +960,7 @@ struct PassView {
     const uint32_t* cpsrc;
     uint32_t* cpdst;
     int64_t cn;
+    int fan;  // 4: a four-way pass (Merge4) over runs of `width`; else two-way
 };
 
 // NEAR (the general plan's candidate, confirmed by merge slot 0 from the tile
@@ -711,12 +972,29 @@ struct PassView {
 
 template <class S>
 __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
-                                                     int64_t n, int M, int64_t T, int k) {
+                                                     int64_t n, int M, int64_t T, int k, bool fan4 = false) {
     PassView<S> v{};
     v.active = false;
     v.split = -1;
     v.cn = 0;
+    v.fan = 2;
     const int path = ctl->path;
+    if (fan4 && path == 3 /* SR_PATH_GENERAL */) {
+        // four-way schedule: slot k (even) merges the levels k and k+1 in one
+        // pass, from runs of T << k to runs of T << (k+2); odd slots are
+        // empty; with M odd the last slot is a two-way pass
+        if ((k & 1) == 0) {
+            const int P = M / 2 + (M & 1);  // passes over the array
+            const int from = (P - k / 2) & 1;
+            v.src = from ? S1 : U;
+            v.dst = from ? U : S1;
+            v.n = n;
+            v.width = T << k;
+            v.active = true;
+            v.fan = k + 1 < M ? 4 : 2;
+        }
+        return v;
+    }
     if (path == 6 /* SR_PATH_NEAR */ && k >= 1) {
         const bool to_s1 = (M & 1) == 0;  // slot 0 wrote S1
         S* X = to_s1 ? S1 : U;
@@ -779,7 +1057,7 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
 
 template <class S>
 __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1, uint32_t* PU, uint32_t* PS1,
-                                                    int64_t n, int M) {
+                                                    int64_t n, int M, bool fan4 = false) {
     // Every field is chosen as a scalar and the view built once at the end:
     // a view assembled field by field on different branches was kept in
     // scratch memory (a per-lane stack slot written on every launch).
@@ -796,7 +1074,8 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         const int64_t m = job ? (int64_t)ctl->m : 0;
         const int P = job ? ctl->job_passes : 0;
         S* X0 = S1 + (n - m);
-        const bool odd = (M & 1) != 0;
+        // passes after the tile sort: M two-way, or M/2 four-way (+1 two-way)
+        const bool odd = ((fan4 && path == 3 ? M / 2 + (M & 1) : M) & 1) != 0;
         src = job ? X0 : U;
         dst = job ? ((P & 1) ? U : X0) : (odd ? S1 : U);
         psrc = job ? nullptr : PU;
@@ -818,6 +1097,7 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
     v.cpsrc = nullptr;
     v.cpdst = nullptr;
     v.cn = 0;
+    v.fan = 2;
     return v;
 }
 

@@ -37,8 +37,8 @@ EXPORTS = ("sr_sort_keys", "sr_sort_pairs", "sr_sort_segmented", "sr_sort_batch"
 SR_MEASURE_INV = 1
 
 # Fields of a tuning-table row (sr_tune_entry) and their "unset" values.
-TUNE_FIELDS = ("tile_variant", "merge_items", "partition", "nontemporal")
-TUNE_UNSET = {"tile_variant": -1, "merge_items": 0, "partition": -1, "nontemporal": -1}
+TUNE_FIELDS = ("tile_variant", "merge_items", "partition", "nontemporal", "fan_in")
+TUNE_UNSET = {"tile_variant": -1, "merge_items": 0, "partition": -1, "nontemporal": -1, "fan_in": 0}
 
 
 class SrStats(ctypes.Structure):
@@ -64,7 +64,7 @@ class SrTuneEntry(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("pairs", ctypes.c_int32), ("min_n", ctypes.c_int64),
                 ("tile_variant", ctypes.c_int32), ("merge_items", ctypes.c_int32),
                 ("partition", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("segmented", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("segmented", ctypes.c_int32), ("fan_in", ctypes.c_int32)]
 
 
 class SrPresortedness(ctypes.Structure):

@@ -106,6 +106,8 @@ def test_tuning_table_validation(lib, keep_table):
         {"dtype": "int32", "min_n": 0, "merge_items": 12},
         {"dtype": "int32", "min_n": 0, "partition": 3},
         {"dtype": "int32", "min_n": 0, "nontemporal": -2},
+        {"dtype": "int32", "min_n": 0, "fan_in": 3},
+        {"dtype": "int32", "pairs": True, "min_n": 0, "fan_in": 4},   # pairs merge two-way
     ]
     for r in bad:
         with pytest.raises(sortrace.SortraceError) as ei:
@@ -121,12 +123,15 @@ def test_tuning_table_validation(lib, keep_table):
     both = sortrace.tune_get()
     assert [(r["min_n"], r["segmented"]) for r in both if r["dtype"] == "int32"] == \
         [(0, False), (1 << 22, False), (0, True)]
-    for r in (dict(seg, partition=1), dict(seg, nontemporal=0)):
+    for r in (dict(seg, partition=1), dict(seg, nontemporal=0), dict(seg, fan_in=4)):
         with pytest.raises(sortrace.SortraceError):
             sortrace.tune_set([r])
     raw = (sortrace.SrTuneEntry * 1)()
     raw[0].tile_variant, raw[0].partition, raw[0].nontemporal, raw[0].segmented = -1, -1, -1, 2
     assert lib.sr_tune_set(raw, 1) == 1 and b"segmented" in lib.sr_last_error_message()
+    four = dict(rows[1], fan_in=4)
+    sortrace.tune_set([rows[0], four])
+    assert [r["fan_in"] for r in sortrace.tune_get()] == [4, 0]   # int32 row first
     sortrace.tune_set(rows)
     e = (sortrace.SrTuneEntry * 1)()
     e[0].dtype = 9
