@@ -10,15 +10,17 @@ the previous band's choice, so that timing noise does not flip rows):
                 (1), or each merge workgroup searching its own window (0);
   nontemporal   persistent merge with nontemporal window loads and stores;
   tile_variant  32-bit keys: 512 x 16 or 1024 x 8 threads x keys per tile;
-  merge_items   32-bit keys, fused merge: 8 or 16 outputs per thread.
+  merge_items   32-bit keys, fused merge: 8 or 16 outputs per thread;
+  fan_in        keys only, with the partition launch: unset (two-way passes)
+                or 4 (four-way passes, each merging two levels of the merge
+                tree in one read and one write of the array).
 
 Segmented and batched sorts (rows with "segmented": true, looked up by the
 total key count) are swept separately on the batched workload's mix --
 log-uniform segment lengths in [16, 262144] -- over tile_variant and
 merge_items (32-bit keys, keys only).
 
-The merge fan-in is 2 on every path (one pass halves the sorted pieces), so
-it is not a swept field.  Inputs are uniform random keys of the band's size
+Pairs always merge two-way.  Inputs are uniform random keys of the band's size
 (the case that runs every merge pass), generated on the device from a fixed
 seed.  Every candidate's output is compared byte for byte with the output
 under the built-in rules, so a table can only select among shapes that sort
@@ -57,7 +59,7 @@ def candidates(dtype: str, pairs: bool) -> list:
     tiles = (0, 1) if wide else (None,)
     for tile, part in itertools.product(tiles, (0, 1)):
         extra = ({"merge_items": m} for m in ((8, 16) if wide else (None,))) if part == 0 else \
-            ({"nontemporal": t} for t in (0, 1))
+            ({"nontemporal": t, **f} for t in (0, 1) for f in (({},) if pairs else ({}, {"fan_in": 4})))
         for e in extra:
             c = {"partition": part}
             if tile is not None:

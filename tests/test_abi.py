@@ -155,10 +155,13 @@ def test_autotune_host_logic(tmp_path, keep_table):
     import json
     from paper_1609_04471_amd import autotune, sortrace
     c = autotune.candidates("int32", False)
-    # 2 tiles x (fused: 2 merge widths + persistent: 2 store kinds)
-    assert len(c) == 8 and len({json.dumps(x, sort_keys=True) for x in c}) == 8
+    # 2 tiles x (fused: 2 merge widths + persistent: 2 store kinds x 2 fan-ins)
+    assert len(c) == 12 and len({json.dumps(x, sort_keys=True) for x in c}) == 12
     assert all(set(x) <= set(sortrace.TUNE_FIELDS) for x in c)
-    for dt, pairs in (("uint64", False), ("int32", True), ("float32", True), ("uint64", True)):
+    assert autotune.candidates("uint64", False) == \
+        [{"partition": 0}, {"partition": 1, "nontemporal": 0}, {"partition": 1, "nontemporal": 0, "fan_in": 4},
+         {"partition": 1, "nontemporal": 1}, {"partition": 1, "nontemporal": 1, "fan_in": 4}]
+    for dt, pairs in (("int32", True), ("float32", True), ("uint64", True)):
         c = autotune.candidates(dt, pairs)
         assert c == [{"partition": 0}, {"partition": 1, "nontemporal": 0}, {"partition": 1, "nontemporal": 1}]
     sizes = autotune.band_sizes("int32", False, 16, 20, 2)
