@@ -1861,7 +1861,9 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         slots[blockIdx.x * 4 + 1] = a + (t4 << kAscBits);
         slots[blockIdx.x * 4 + 2] = t2;
         slots[blockIdx.x * 4 + 3] = t3;
-        __threadfence();
+        // release: the slot is written back to memory before the ticket moves
+        // (no acquire here: nothing this workgroup reads later depends on it)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         // two-level ticket: groups of kProbeGroup workgroups share a counter
         // (each on its own 256-byte line), the last of a group bumps ctl->ticket
         const unsigned int groups = (gridDim.x + kProbeGroup - 1) / kProbeGroup;
@@ -1876,7 +1878,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     }
     __syncthreads();
     if (last) {
-        __threadfence();
+        // acquire: the slots of every workgroup, released before their tickets
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         unsigned long long acc[4] = {0, 0, 0, 0};
         for (int g = tid; g < (int)gridDim.x; g += kProbeWG)
             for (int q = 0; q < 4; ++q) acc[q] += __hip_atomic_load(&slots[g * 4 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
