@@ -67,9 +67,10 @@ typedef enum {
                               already in order joined, then a merge tree over the
                               remaining leaves (Sec. 3 natural runs, Sec. 2 Mono) */
     SR_PATH_FEW = 5,       /* few distinct keys (keys only): equal buckets around at
-                              most 64 sampled values -- the GPU form of 3-way
-                              partitioning (Sec. 4, k-limited of Sec. 2); keys
-                              between the sampled values are sorted separately */
+                              most 4096 sampled values -- the GPU form of 3-way
+                              partitioning (Sec. 4, k-limited of Sec. 2, Table 1's
+                              12-limited few-unique type); keys between the
+                              sampled values are sorted separately */
     SR_PATH_NEAR = 6       /* tile sort, then two rounds of neighbour merges: tile
                               pairs (0,1),(2,3),... and then (1,2),(3,4),...; taken
                               when the sorted tiles show that every tile overlaps

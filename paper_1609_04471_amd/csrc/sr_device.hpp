@@ -73,6 +73,8 @@ struct Ctl {
     int dual;                         // OUTLIER beside a run plan (the sample's turning points are rare)
     unsigned long long reserved[4];   // [0] descents, [1] ascents (for sr_last_stats)
     unsigned long long run[4];        // RUNS: merge leaves, merge passes, keys reversed, keys in dense pieces
+    int few_wide;                     // FEW: the job uses the wide tables (more than 64 splitters)
+    int pad_w;
 };
 
 // Plain relaxed agent-scope accessors (coherent across the XCDs' L2s), for

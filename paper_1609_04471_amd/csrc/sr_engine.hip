@@ -1010,6 +1010,187 @@ __device__ __forceinline__ void few_place(typename C::S* U, const typename C::S*
     }
 }
 
+// ------------------------------------------------------ wide few unique
+// The FEW job with 65 to 4096 sampled values (Table 1's few-unique type is
+// 12-limited: 4096 values).  Buckets and job are those above; what changes
+// with the count: the probe samples kWideSample keys into a larger hash set
+// and sorts the distinct values with the tile sorter; a key's bucket is a
+// branch-free binary search over the splitters in LDS; a tile's counts are
+// 16-bit LDS counters (a tile holds 4096 keys) added to one global counter
+// per bucket; the offsets come from a scan across the verify workgroup; the
+// fill pass reads its tables through the cache.  A 16384-key sample of 4096
+// values misses about 2 % of them (4096 e^-4); their keys are between keys.
+constexpr int kWideMax = 4096;
+constexpr int kWideBuckets = 2 * kWideMax + 1;
+constexpr int kWideSample = 16384;
+constexpr int kWideHash = 8192;  // LDS hash set slots (codes of the key type)
+
+// In the look-back area of the workspace; the probe clears the counters a
+// wide job will use.
+struct WideTable {
+    unsigned long long ns;                   // splitters
+    unsigned long long split[kWideMax];      // codes, ascending, distinct
+    unsigned long long cnt[kWideBuckets];    // keys per bucket
+    long long off[kWideBuckets + 1];         // first output position of each bucket
+    long long bpre[kWideBuckets];            // between keys in earlier buckets
+    unsigned long long sample[kWideMax];     // the probe's distinct samples (raw keys), sorted in place
+};
+
+// Splitters below code u: binary search over sp[0, P) without branches (P a
+// power of two; entries past the splitters hold the largest code).
+template <class U>
+__device__ __forceinline__ int wide_below(const U* sp, int P, U u) {
+    int base = 0;
+    for (int half = P >> 1; half > 0; half >>= 1) base = sp[base + half] < u ? base + half : base;
+    return base + (sp[base] < u ? 1 : 0);
+}
+
+template <class U>
+struct WideLds {
+    U sp[kWideMax];                              // splitter codes, padded with the largest code
+    unsigned int hist[(kWideBuckets + 1) / 2];   // two 16-bit counters per word
+};
+
+// Bucket counts and between keys of the 4096-key tile [c0, c1) (256 threads).
+template <class C>
+__device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int64_t c1, Ctl* ctl, WideTable* fw,
+                           typename C::S* s1, WideLds<typename C::U>& fl) {
+    using U = typename C::U;
+    constexpr int R = kClsTC / kClsWG;
+    static_assert(kClsTC < 65536, "16-bit tile counters");
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int ns = (int)fw->ns;
+    const int nb = 2 * ns + 1;
+    int P = 1;
+    while (P < ns) P <<= 1;
+    for (int i = tid; i < P; i += kClsWG) fl.sp[i] = i < ns ? (U)fw->split[i] : (U)~(U)0;
+    for (int w = tid; w < (nb + 1) / 2; w += kClsWG) fl.hist[w] = 0u;
+    typename C::S x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + r * kClsWG + tid;
+        if (q < c1) x[r] = keys[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + r * kClsWG + tid;
+        bool between = false;
+        if (q < c1) {
+            const U u = C::enc(x[r]);
+            const int lo = wide_below<U>(fl.sp, P, u);
+            const int b = (lo < ns && fl.sp[lo] == u) ? 2 * lo + 1 : 2 * lo;
+            atomicAdd(&fl.hist[b >> 1], 1u << ((b & 1) * 16));
+            between = (b & 1) == 0;
+        }
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(between);
+        if (mask != 0ull) {
+            const int leader = __builtin_ctzll(mask);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&ctl->m, (unsigned long long)__builtin_popcountll(mask));
+            base = __shfl(base, leader);
+            if (between) {
+                const unsigned long long rank = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+                s1[n - 1 - (int64_t)(base + rank)] = x[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int w = tid; w < (nb + 1) / 2; w += kClsWG) {
+        const unsigned int h = fl.hist[w];
+        if (h & 0xFFFFu) atomicAdd(&fw->cnt[2 * w], (unsigned long long)(h & 0xFFFFu));
+        if ((h >> 16) != 0u && 2 * w + 1 < nb) atomicAdd(&fw->cnt[2 * w + 1], (unsigned long long)(h >> 16));
+    }
+}
+
+// Offsets (a scan across the verify workgroup, kWideBuckets / kVerWG buckets
+// per thread) and the job.
+__device__ void wide_plan(Ctl* ctl, int64_t n, WideTable* fw, int64_t T_sort) {
+    constexpr int PB = (kWideBuckets + kVerWG - 1) / kVerWG;
+    __shared__ long long s_w[kVerWG / kWave];
+    __shared__ long long s_bw[kVerWG / kWave];
+    const int ns = (int)fw->ns;
+    const int nb = 2 * ns + 1;
+    const int b0 = (int)threadIdx.x * PB;
+    unsigned long long t[PB];
+    long long sum = 0, bsum = 0;
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+        const int b = b0 + q;
+        t[q] = b < nb ? ld_agent(&fw->cnt[b]) : 0ull;
+        sum += (long long)t[q];
+        if ((b & 1) == 0) bsum += (long long)t[q];
+    }
+    long long total, btotal;
+    long long o = wg_scan_excl(sum, s_w, total);
+    long long bp = wg_scan_excl(bsum, s_bw, btotal);
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+        const int b = b0 + q;
+        if (b < nb) {
+            fw->off[b] = o;
+            fw->bpre[b] = bp;
+        }
+        o += (long long)t[q];
+        if ((b & 1) == 0) bp += (long long)t[q];
+    }
+    if (threadIdx.x != 0) return;
+    fw->off[nb] = total;
+    const unsigned long long m = ld_agent(&ctl->m);
+    if (total != n || (unsigned long long)btotal != m || 4 * m > (unsigned long long)n) {
+        ctl->path = SR_PATH_GENERAL;
+        ctl->m = 0;
+        ctl->job_passes = 0;
+        return;
+    }
+    ctl->job_passes = ceil_log2_dev(((int64_t)m + T_sort - 1) / T_sort);
+}
+
+// Merge slot P of a wide FEW job: as few_place, with the tables read through
+// the cache.
+template <class C, int WG>
+__device__ __forceinline__ void wide_place(typename C::S* U, const typename C::S* X0, int64_t n,
+                                           const WideTable* fw) {
+    using S = typename C::S;
+    constexpr int IT = 8;
+    const int tid = threadIdx.x;
+    const int nb = 2 * (int)fw->ns + 1;
+    const long long* off = fw->off;
+    const long long* bpre = fw->bpre;
+    for (int64_t base = (int64_t)blockIdx.x * WG * IT; base < n; base += (int64_t)gridDim.x * WG * IT) {
+        const int64_t p0 = base + (int64_t)tid * IT;
+        if (p0 >= n) continue;
+        int lo = 0, hi = nb - 1;  // last bucket starting at or before p0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= p0) lo = mid;
+            else hi = mid - 1;
+        }
+        int b = lo;
+        constexpr int VN = 16 / sizeof(S);
+        V16<S> v[IT / VN];
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int64_t p = p0 + r;
+            S val{};
+            if (p < n) {
+                while (off[b + 1] <= p) ++b;
+                val = (b & 1) ? C::dec((typename C::U)fw->split[b >> 1]) : X0[bpre[b] + (p - off[b])];
+            }
+            v[r / VN].v[r % VN] = val;
+        }
+        if (p0 + IT <= n && aligned16(U + p0)) {
+#pragma unroll
+            for (int q = 0; q < IT / VN; ++q) reinterpret_cast<V16<S>*>(U + p0)[q] = v[q];
+        } else {
+#pragma unroll
+            for (int r = 0; r < IT; ++r)
+                if (p0 + r < n) U[p0 + r] = v[r / VN].v[r % VN];
+        }
+    }
+}
+
 // ============================================================== kernels
 
 // Tile-sort launch.  GENERAL / OUTLIER: the tile sort of the job's array
@@ -1148,7 +1329,8 @@ template <class C, int WG, int IT, bool PAIRS>
 __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S1, uint32_t* PU, uint32_t* PS1,
                                               int64_t n, int M, int64_t T, int k, const Ctl* ctl,
                                               const RunArea* ra, const FewTable* ft,
-                                              const unsigned long long* tdesc = nullptr) {
+                                              const unsigned long long* tdesc = nullptr,
+                                              const WideTable* fw = nullptr) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename MC::Smem sm;
@@ -1161,7 +1343,8 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
         if (ctl != nullptr) {
             const int path = ctl->path;
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
-                few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
+                if (fw != nullptr && ctl->few_wide) wide_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, fw);
+                else few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
             }
         }
@@ -1189,7 +1372,7 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
                                                       const int64_t* co, const Ctl* ctl, const RunArea* ra,
                                                       const FewTable* ft, const unsigned long long* tdesc = nullptr,
-                                                      int fan4 = 0) {
+                                                      int fan4 = 0, const WideTable* fw = nullptr) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
     using MC = typename MP::MC;
     using S = typename C::S;
@@ -1206,7 +1389,8 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         if (ctl != nullptr) {
             const int path = ctl->path;
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
-                few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
+                if (fw != nullptr && ctl->few_wide) wide_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, fw);
+                else few_place<C, WG>(U, S1 + (n - (int64_t)ctl->m), n, ft, &sm);
                 return;
             }
         }
@@ -1265,18 +1449,24 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
                                                      unsigned int* flags, unsigned long long* tfirst,
                                                      unsigned long long* tlast, unsigned long long* tcount,
                                                      int runs_ok, RunTile* rdesc, FewTable* ft,
-                                                     typename C::S* s1) {
+                                                     typename C::S* s1, WideTable* fw) {
     using U = typename C::U;
+    // the outlier window and the wide few-unique tables share the launch's LDS
+    __shared__ union {
+        U sk[kClsW];
+        WideLds<U> wide;
+    } cls_lds;
     const int path = ctl->path;
     if (path == SR_PATH_FEW) {
         const int64_t f0 = (int64_t)blockIdx.x * kClsTC;
         const int64_t f1 = (f0 + kClsTC) < n ? (f0 + kClsTC) : n;
-        few_count<C>(keys, n, f0, f1, ctl, ft, s1);
+        if (fw != nullptr && ctl->few_wide) wide_count<C>(keys, n, f0, f1, ctl, fw, s1, cls_lds.wide);
+        else few_count<C>(keys, n, f0, f1, ctl, ft, s1);
         return;
     }
     const bool do_runs = runs_ok && (path == SR_PATH_RUNS || (path == SR_PATH_OUTLIER && ctl->dual));
     if (path != SR_PATH_OUTLIER && !do_runs) return;
-    __shared__ U sk[kClsW];
+    U* sk = cls_lds.sk;
     __shared__ unsigned int kw[kClsWG], rw[kClsWG];   // per-thread kept masks, removals by others
     __shared__ int wtot[kClsWG / kWave];
     __shared__ int s_flag[2], s_both[2];
@@ -1562,10 +1752,12 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
                                                    const unsigned long long* tlast, const unsigned long long* tcount,
                                                    unsigned long long* kpref_t, int64_t T_sort,
                                                    const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
-                                                   int runs_ok, int64_t merge_ch, int M, FewTable* ft) {
+                                                   int runs_ok, int64_t merge_ch, int M, FewTable* ft,
+                                                   WideTable* fw) {
     const int path0 = ctl->path;
     if (path0 == SR_PATH_FEW) {
-        few_plan(ctl, n, ft, T_sort);
+        if (fw != nullptr && ctl->few_wide) wide_plan(ctl, n, fw, T_sort);
+        else few_plan(ctl, n, ft, T_sort);
         return;
     }
     const bool want_runs = runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->dual));
@@ -1705,7 +1897,7 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
 template <class C>
 __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, int64_t n, Ctl* ctl,
                                                     unsigned long long* slots, int jobs_ok, int runs_pmax,
-                                                    FewTable* ft) {
+                                                    FewTable* ft, WideTable* fw) {
     using U = typename C::U;
     using S = typename C::S;
     constexpr int VN = 16 / sizeof(S);
@@ -1923,7 +2115,9 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         if (!mixed && desc == 0) path = SR_PATH_SORTED;
         else if (!mixed && asc == 0) path = SR_PATH_REVERSED;
         else if (outlier_ok && sdesc * 16 <= spairs && !drops) path = SR_PATH_OUTLIER;
-        else if (few_ok && sequal * 128 >= spairs) path = SR_PATH_FEW;  // confirmed by the sample below
+        // few distinct values: equal neighbours at a rate of at least 1/16384
+        // (about 1/v for v values); confirmed by the sample below
+        else if (few_ok && sequal * 16384 >= spairs) path = SR_PATH_FEW;
         else if (runs_like) path = SR_PATH_RUNS;
         else path = SR_PATH_GENERAL;
         const int force = ctl->force_path;
@@ -1944,6 +2138,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     if (last) {
         __syncthreads();
         int path = s_path;
+        int few_wide = 0;
         if (path == SR_PATH_FEW || path <= -10) {
             // FEW: the distinct values among kFewSample evenly spread samples
             // become the splitters if there are at most kFewMax of them.  They
@@ -1958,9 +2153,21 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             constexpr int HB = 11, HS = 1 << HB;
             static_assert(HS >= 2 * kFewSample, "the hash set stays at most half full");
             static_assert(kFewMax <= kWave, "one splitter per lane");
-            __shared__ unsigned long long hset[HS];
+            using FS = TileSort<C, kProbeWG, kFewSample / kProbeWG, false>;
+            using FSW = TileSort<C, kProbeWG, kWideMax / kProbeWG, false>;
+            static_assert(FS::T == kFewSample && FSW::T == kWideMax, "one sample tile");
+            constexpr int WB = 8;  // wide sample keys per thread per round
+            static_assert(kWideHash >= kWideMax + kProbeWG * WB + 1, "inserts stop before the wide hash set fills");
+            // the phases run one after another, so their LDS is shared
+            __shared__ union {
+                unsigned long long hset[HS];
+                U wh[kWideHash];
+                typename FSW::Smem fsw;
+                typename FS::Smem fsm;
+            } few_lds;
+            unsigned long long* hset = few_lds.hset;
             __shared__ unsigned long long hval[kFewMax];
-            __shared__ int s_dist, s_top, s_nv;
+            __shared__ int s_dist, s_top, s_nv, s_full;
             for (int i = tid; i < HS; i += kProbeWG) hset[i] = 0ull;
             if (tid == 0) {
                 s_dist = 0;
@@ -2006,15 +2213,73 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                     if (lane < total) ft->split[lane] = (unsigned long long)v[0];
                 }
                 ns = total;
-            } else if (s_force) {
-                using FS = TileSort<C, kProbeWG, kFewSample / kProbeWG, false>;
-                static_assert(FS::T == kFewSample, "one sample tile");
-                __shared__ typename FS::Smem fsm;
+            } else if (fw != nullptr) {
+                // wide: kWideSample keys in rounds of WB per thread into a
+                // larger hash set of codes (code + 1, as above), until more
+                // than kWideMax distinct ones are seen; a round starts only
+                // while at most kWideMax are known, so the set never fills.
+                // Up to kWideMax values are then sorted as one tile.
+                __syncthreads();  // the small hash set is dead from here
+                U* wh = few_lds.wh;
+                for (int i = tid; i < kWideHash; i += kProbeWG) wh[i] = (U)0;
+                if (tid == 0) {
+                    s_dist = 0;
+                    s_top = 0;
+                    s_nv = 0;
+                    s_full = 0;
+                }
+                __syncthreads();
+                constexpr int PERW = kWideSample / kProbeWG;
+                for (int b0 = 0; b0 < PERW; b0 += WB) {
+                    if (s_full) break;
+                    U sv2[WB];
+#pragma unroll
+                    for (int r = 0; r < WB; ++r)
+                        sv2[r] = C::enc(keys[(int64_t)(tid * PERW + b0 + r) * n / kWideSample]);
+#pragma unroll
+                    for (int r = 0; r < WB; ++r) {
+                        const U code = (U)(sv2[r] + (U)1);
+                        if (code == (U)0) {
+                            s_top = 1;
+                            continue;
+                        }
+                        unsigned int h =
+                            (unsigned int)(((unsigned long long)code * 0x9E3779B97F4A7C15ull) >> 51) & (kWideHash - 1);
+                        for (;;) {  // ends: fewer than kWideHash distinct codes are ever inserted
+                            const U old = atomicCAS(&wh[h], (U)0, code);
+                            if (old == (U)0) {
+                                if (atomicAdd(&s_dist, 1) + 1 > kWideMax) s_full = 1;
+                                break;
+                            }
+                            if (old == code) break;
+                            h = (h + 1u) & (kWideHash - 1);
+                        }
+                    }
+                    __syncthreads();
+                }
+                const int wtotal = s_dist + s_top;
+                if (!s_full && wtotal <= kWideMax) {
+                    S* samp = reinterpret_cast<S*>(fw->sample);
+                    for (int i = tid; i < kWideHash; i += kProbeWG) {
+                        const U c = wh[i];
+                        if (c != (U)0) samp[atomicAdd(&s_nv, 1)] = C::dec((U)(c - (U)1));
+                    }
+                    if (tid == 0 && s_top) samp[s_dist] = C::dec((U)~(U)0);
+                    __syncthreads();  // the hash set is dead from here: its LDS is the sorter's
+                    FSW::run(few_lds.fsw, samp, samp, nullptr, nullptr, wtotal);
+                    __syncthreads();
+                    for (int i = tid; i < wtotal; i += kProbeWG) fw->split[i] = (unsigned long long)C::enc(samp[i]);
+                    ns = wtotal;
+                    few_wide = 1;
+                }
+                __syncthreads();
+            }
+            if (ns < 0 && total > kFewMax && s_force) {
                 __shared__ int s_cnt[kProbeWG / kWave];
                 S* samp = reinterpret_cast<S*>(ft->sample);
                 for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[(int64_t)i * n / kFewSample];
                 __syncthreads();
-                FS::run(fsm, samp, samp, nullptr, nullptr, kFewSample);
+                FS::run(few_lds.fsm, samp, samp, nullptr, nullptr, kFewSample);
                 __syncthreads();
                 int c = 0;
                 bool first[PER];
@@ -2045,9 +2310,14 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             }
             __syncthreads();
             if (ns >= 0) {
-                for (int b = tid; b < kFewCopies * (2 * ns + 1); b += kProbeWG)
-                    st_agent(&ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)], 0ull);
-                if (tid == 0) ft->ns = (unsigned long long)ns;
+                if (few_wide) {
+                    for (int b = tid; b < 2 * ns + 1; b += kProbeWG) st_agent(&fw->cnt[b], 0ull);
+                    if (tid == 0) fw->ns = (unsigned long long)ns;
+                } else {
+                    for (int b = tid; b < kFewCopies * (2 * ns + 1); b += kProbeWG)
+                        st_agent(&ft->cnt[b / (2 * ns + 1)][b % (2 * ns + 1)], 0ull);
+                    if (tid == 0) ft->ns = (unsigned long long)ns;
+                }
                 path = SR_PATH_FEW;
             } else {
                 path = -path - 10;
@@ -2059,6 +2329,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             path = SR_PATH_NEAR;
         if (tid == 0) {
             ctl->path = path;
+            ctl->few_wide = path == SR_PATH_FEW ? few_wide : 0;
             ctl->dual = s_dual;
             ctl->reserved[0] = s_desc;  // kept for sr_last_stats
             ctl->reserved[1] = s_asc;
@@ -2728,7 +2999,8 @@ size_t aux_bound(int64_t n) {
     const size_t ncls = (size_t)cdiv(n, kClsTC);
     const size_t cls_arr = round_up(round_up(ncls, (size_t)kVerRound) * 8, 256);
     return 4 * cls_arr + round_up(ncls * (kClsTC / 8), 256) + round_up(ncls * sizeof(RunTile), 256) +
-           round_up(sizeof(RunArea), 256) + round_up((size_t)cdiv(n, 4096) * 32, 256);
+           round_up(sizeof(RunArea), 256) + round_up((size_t)cdiv(n, 4096) * 32, 256) +
+           round_up(sizeof(WideTable), 256);
 }
 
 void* ws_data(Workspace* ws) { return ws->base; }
@@ -2919,8 +3191,10 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         near_ok = g_near_enabled && M >= 3 && !fan4;
     }
     const size_t tdesc_bytes = near_ok ? round_up((size_t)ntiles * 32, 256) : 0;
+    // FEW with more than 64 splitters: its tables
+    const size_t wide_bytes = few_ok ? round_up(sizeof(WideTable), 256) : 0;
     const size_t data_need = co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0);
-    const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes + tdesc_bytes;
+    const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes + tdesc_bytes + wide_bytes;
     sr_status s;
     if (capturing && !(noalloc ? noalloc_ready() : workspace_fits(st, data_need, aux_need)))
         return fail(SR_ERR_UNSUPPORTED, "a sort recorded into a stream capture cannot allocate or synchronize: "
@@ -2948,6 +3222,9 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         near_ok ? reinterpret_cast<unsigned long long*>(static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes +
                                                         rdesc_bytes + rarea_bytes)
                 : nullptr;
+    WideTable* fw = few_ok ? reinterpret_cast<WideTable*>(static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes +
+                                                          rdesc_bytes + rarea_bytes + tdesc_bytes)
+                           : nullptr;
 
     {
         ProfScope ps(ls, "probe");
@@ -2961,7 +3238,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         const int runs_pmax = M - (int)std::ceil(kRunScanUs / pass_us);
         hipLaunchKernelGGL(k_probe<C>, dim3(g), dim3(kProbeWG), 0, ls, (const S*)keys, n, ctl, ws_slots(ws),
                            (outlier_ok ? 1 : 0) | (runs_ok ? 2 : 0) | (few_ok ? 4 : 0) | (near_ok ? 8 : 0), runs_pmax,
-                           ftab);
+                           ftab, fw);
         SR_LAUNCH_CHECK("probe");
     }
     if (scan_ok) {
@@ -2978,7 +3255,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         {
             ProfScope ps(ls, "classify");
             hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n, ctl,
-                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc, ftab, skeys);
+                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc, ftab, skeys, fw);
             SR_LAUNCH_CHECK("classify");
         }
         {
@@ -2986,7 +3263,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
             hipLaunchKernelGGL(k_verify<C>, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
                                (const unsigned long long*)tcount, kpref_t, (int64_t)T, (const S*)keys,
-                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab);
+                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab, fw);
             SR_LAUNCH_CHECK("verify");
         }
         ProfScope ps(ls, "scatter");
@@ -3048,7 +3325,8 @@ tile_done:
                 const int64_t grid = std::min<int64_t>(nchunks, resident_blocks(kern, TN::MWG));
                 hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
                                    (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
-                                   (const FewTable*)ftab, (const unsigned long long*)tdesc, fan4 ? 1 : 0);
+                                   (const FewTable*)ftab, (const unsigned long long*)tdesc, fan4 ? 1 : 0,
+                                   (const WideTable*)fw);
                 SR_LAUNCH_CHECK("merge");
             }
             if (four) {
@@ -3072,7 +3350,7 @@ tile_done:
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)(cdiv(n, TN::MWG * 8) + extra)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                        (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
-                                       (const unsigned long long*)tdesc);
+                                       (const unsigned long long*)tdesc, (const WideTable*)fw);
                     done = true;
                 }
             }
@@ -3080,7 +3358,7 @@ tile_done:
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)(nchunks + extra)),
                                    dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                    (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
-                                   (const unsigned long long*)tdesc);
+                                   (const unsigned long long*)tdesc, (const WideTable*)fw);
             SR_LAUNCH_CHECK("merge");
         }
     }

@@ -31,15 +31,28 @@ def test_few_unique_type(gpu, n):
     assert st["passes"] == 1, st
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8, 12])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8, 10, 12, 14, 16])
 def test_k_limited(gpu, k):
     n = 1_000_003
     a = inputs.class_int32("limited", n, k, seed=k)
     st = check(gpu, a)
-    if k <= 6:
+    if k <= 12:   # at most 4096 values: the bucket pass
         assert st["path"] == "few", st
-    else:  # more distinct values than splitters
-        assert st["path"] != "few" or st["outliers"] > 0, st
+    else:         # more distinct values than splitters
+        assert st["path"] != "few", st
+
+
+@pytest.mark.parametrize("n", [65_537, 2_000_000, 4_500_017])
+def test_twelve_limited_type(gpu, n):
+    """Table 1's few-unique type is 12-limited: 4096 values.  The sample sees
+    nearly all of them; the keys of the few it misses are sorted as between
+    keys.  At 65,537 keys the probe's pairs hold about one equal neighbour, too
+    few to call the input few-valued: exact either way."""
+    a = inputs.class_int32("limited", n, 12, seed=n)
+    st = check(gpu, a)
+    if n >= 1_000_000:
+        assert st["path"] == "few", st
+        assert st["outliers"] <= n // 8, st
 
 
 # The 2,000,000-key, 0.1 % case took a GPU memory fault under a rewrite of
@@ -124,10 +137,11 @@ def test_forced_and_switched_off(gpu):
         gpu.set_option("few_path", 1)
 
 
-@pytest.mark.parametrize("distinct,few", [(64, True), (65, False)])
+@pytest.mark.parametrize("distinct,few", [(64, True), (65, True), (3000, True), (6000, False)])
 def test_distinct_count_limit(gpu, distinct, few):
-    """The probe keeps FEW for at most 64 distinct sampled values: 64 values
-    spread evenly (every one sampled) take the bucket pass, 65 do not."""
+    """The probe keeps FEW while its sample holds at most 4096 distinct values:
+    up to 64 are sorted by one wavefront, more by the tile sorter (65 and 3000
+    values); 6000 values fill the sample's limit and the sort goes general."""
     n = 1_000_003
     rng = np.random.default_rng(distinct)
     vals = np.unique(rng.integers(-2**31, 2**31, size=4 * distinct, dtype=np.int64))[:distinct]
@@ -151,3 +165,52 @@ def test_extreme_codes_in_the_sample(gpu):
     a = ivals[rng.integers(0, ivals.size, size=n)]
     st = check(gpu, a, "int32")
     assert st["path"] == "few", st
+
+
+@pytest.mark.parametrize("dtype", ["float32", "uint64"])
+def test_many_values_other_dtypes(gpu, dtype):
+    """2000 distinct values (with the extreme codes among them) in float32 and
+    uint64: splitters sorted by the tile sorter, buckets found by the
+    branch-free search."""
+    n = 3_000_001
+    rng = np.random.default_rng(31)
+    if dtype == "float32":
+        vals = np.unique(rng.standard_normal(2000).astype(np.float32))
+        vals[:4] = np.array([0x7FC00000, 0xFFFFFFFF, 0x80000000, 0x00000000], dtype=np.uint32).view(np.float32)
+    else:
+        vals = np.unique(rng.integers(1, 2**63, size=2000, dtype=np.uint64) * np.uint64(2))
+        vals[:2] = np.array([0, 2**64 - 1], dtype=np.uint64)
+    a = vals[rng.integers(0, vals.size, size=n)]
+    st = check(gpu, a, dtype)
+    assert st["path"] == "few", st
+
+
+def test_forced_few_with_many_values(gpu):
+    """Forced FEW on keys with more than 4096 distinct values: the splitters
+    are the 64 smallest distinct values of 1024 sorted sample keys; the rest
+    are between keys, too many for the bucket pass, so the plan falls back,
+    exactly."""
+    gpu.set_option("force_path", 5)
+    try:
+        a = inputs.class_int32("limited", 1_000_003, 16, seed=3)
+        st = check(gpu, a)
+    finally:
+        gpu.set_option("force_path", -1)
+    assert st["path"] in ("few", "general"), st
+
+
+@pytest.mark.parametrize("n", [100_000, 2_000_000])
+@pytest.mark.parametrize("frac", [0.001, 0.03])
+def test_wide_between_keys(gpu, n, frac):
+    """1500 values (the wide tables) and a fraction of other keys: the between
+    keys are sorted on their own (several merge passes at 3 %) and placed
+    between the equal buckets."""
+    rng = np.random.default_rng(int(n * frac * 1000) % 2**32 + 7)
+    vals = np.unique(rng.integers(-2**31, 2**31, size=1500, dtype=np.int64))
+    a = vals[rng.integers(0, vals.size, size=n)]
+    other = rng.random(n) < frac
+    a[other] = rng.integers(-2**31, 2**31, size=int(other.sum()), dtype=np.int64)
+    a = a.astype(np.int32)
+    st = check(gpu, a)
+    if n >= 1_000_000:
+        assert st["path"] == "few" and st["outliers"] > 0, st
