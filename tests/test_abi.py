@@ -182,4 +182,5 @@ def test_autotune_host_logic(tmp_path, keep_table):
     # the shipped table names only swept shapes
     for r in autotune.validate(json.load(open(sortrace.TUNE_TABLE))):
         shape = {k: v for k, v in r.items() if k in sortrace.TUNE_FIELDS}
-        assert shape in autotune.candidates(r["dtype"], r["pairs"]), r
+        swept = autotune.seg_candidates(r["dtype"]) if r["segmented"] else autotune.candidates(r["dtype"], r["pairs"])
+        assert shape in swept, r

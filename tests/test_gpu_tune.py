@@ -120,12 +120,13 @@ def test_shipped_table_is_valid_and_loaded(gpu):
     rows = autotune.validate(json.load(open(gpu.TUNE_TABLE)))
     for r in rows:
         shape = {k: v for k, v in r.items() if k in gpu.TUNE_FIELDS}
-        assert shape in autotune.candidates(r["dtype"], r["pairs"]), r
+        swept = autotune.seg_candidates(r["dtype"]) if r["segmented"] else autotune.candidates(r["dtype"], r["pairs"])
+        assert shape in swept, r
     if "SR_TUNE_TABLE" not in os.environ:
         got = gpu.tune_get()
-        want = sorted(rows, key=lambda r: (gpu.DTYPES[r["dtype"]], r["pairs"], r["min_n"]))
-        assert [(g["dtype"], g["pairs"], g["min_n"]) for g in got] == \
-            [(w["dtype"], w["pairs"], w["min_n"]) for w in want]
+        want = sorted(rows, key=lambda r: (gpu.DTYPES[r["dtype"]], r["pairs"], r["segmented"], r["min_n"]))
+        assert [(g["dtype"], g["pairs"], g["segmented"], g["min_n"]) for g in got] == \
+            [(w["dtype"], w["pairs"], w["segmented"], w["min_n"]) for w in want]
 
 
 @pytest.mark.parametrize("tile_variant,merge_items", [(0, 8), (1, 8), (1, 16), (0, 16)])
