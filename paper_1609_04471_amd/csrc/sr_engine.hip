@@ -1282,8 +1282,8 @@ __global__ __launch_bounds__(WG) void k_tile_sort(typename C::S* U, typename C::
     // the general plan's tiles describe themselves for merge slot 0's NEAR test
     unsigned long long* desc =
         (tdesc != nullptr && ctl != nullptr && ctl->path == SR_PATH_NEAR) ? tdesc + 4 * blockIdx.x : nullptr;
-    TS::run(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
-            valid, desc);
+    TS::body(sm, v.src + base, v.dst + base, PAIRS ? v.psrc + base : nullptr, PAIRS ? v.pdst + base : nullptr,
+             valid, desc);
 }
 
 // Merge Path partition of merge slot k: co[c] = co-rank of the start of

@@ -51,8 +51,21 @@ struct TileSort {
     // the banks at most twice per wavefront access instead of IT times.
     static constexpr int TP = T + T / 32;
     static __device__ __forceinline__ int pad(int e) { return e + (e >> 5); }
+
+    // Keys only: a run of width w starts at logical slot G + q * (w + G) and
+    // is followed by G slots holding the largest code (G more lead the first
+    // run), so an exhausted run reads as the largest code and the serial
+    // merge needs no bounds tests.  Ties go to the left run, so the left run
+    // can be read up to IT - 1 slots past its end (only while every remaining
+    // output is the largest code): G >= IT.  Logical slot l lives at pad(l),
+    // like the pairs layout, so lanes whose heads lie IT/2 slots apart do not
+    // meet in the same LDS banks.
+    static constexpr int G = IT < 4 ? 4 : IT;
+    static constexpr int TK = G + T + (T / (kWave * IT)) * G;
+    static constexpr int TKP = TK + TK / 32 + 1;
+    static constexpr int KW = PAIRS ? TP : (TKP > TP ? TKP : TP);
     struct Smem {
-        U k[TP];
+        U k[KW];
         uint32_t p[PAIRS ? TP : 1];    // tile position of each element
         uint32_t pay[PAIRS ? T : 1];   // payload, by tile position
     };
@@ -118,6 +131,106 @@ struct TileSort {
         }
     }
 
+    // Keys only: the IT outputs of thread tid (positions tid*IT .. of runs of
+    // width w) to the gapped layout; threads below the gap count fill the
+    // gaps after the runs with the largest code.
+    static __device__ __forceinline__ void put_k(Smem& sm, int w, int tid, const U (&v)[IT]) {
+        const int out0 = tid * IT;
+        const int q = out0 >> __builtin_ctz((unsigned)w);   // w is a power of two
+        const int l0 = G + q * (w + G) + (out0 - q * w);
+#pragma unroll
+        for (int r = 0; r < IT; ++r) sm.k[pad(l0 + r)] = v[r];
+        const int runs = T / w;
+        if (w < T && tid < runs * G) {
+            const int q2 = tid / G;
+            sm.k[pad(G + q2 * (w + G) + w + (tid - q2 * G))] = key_max<U>();
+        }
+    }
+
+    // Keys only: one merge level in the gapped layout, runs of width w become
+    // runs of 2w; thread tid produces outputs [tid*IT, tid*IT + IT) of its
+    // group.  The co-rank search takes fixed power-of-two steps (no exit
+    // test per lane); the serial merge reads both run heads each step.
+    // Byte offset of logical slot l in the keys-only layout, (l + l/32) *
+    // sizeof(U), as one shift and one add-shift (the compiler's own form of
+    // this expression takes three instructions).
+    static __device__ __forceinline__ uint32_t slot_bytes(uint32_t l) {
+        constexpr int SH = sizeof(U) == 8 ? 3 : 2;
+        uint32_t t, r;
+        asm("v_lshrrev_b32 %0, 5, %1" : "=v"(t) : "v"(l));
+        asm("v_add_lshl_u32 %0, %1, %2, %3" : "=v"(r) : "v"(l), "v"(t), "i"(SH));
+        return r;
+    }
+
+    static __device__ __forceinline__ void lds_level_k(const Smem& sm, int w, int tid, U (&v)[IT]) {
+        using LU = const __attribute__((address_space(3))) U;   // 32-bit LDS addresses
+        using LB = const __attribute__((address_space(3))) char;
+        LB* kb = (LB*)sm.k;
+        auto ld = [kb](int l) { return *(LU*)(kb + slot_bytes((uint32_t)l)); };
+        const int out0 = tid * IT;
+        const int g = out0 >> (__builtin_ctz((unsigned)w) + 1);   // w is a power of two
+        const int d = out0 - g * 2 * w;
+        const int a0 = G + 2 * g * (w + G);
+        const int b0 = a0 + w + G;
+        const int lo = d > w ? d - w : 0;
+        const int hi = d < w ? d : w;
+        // i = lo + the number of x in [lo, hi) with A[x] <= B[d-1-x].  Probe
+        // t reads A[t-1] and B[d-t]; i <= hi <= w and s <= w keep both
+        // inside [a0 - 1, b0 + w] even when t > hi (then the probe is void).
+        int i = lo;
+#pragma unroll 1
+        for (int s = w; s >= 1; s >>= 1) {
+            const int t = i + s;
+            const bool ok = (t <= hi) & (ld(a0 - 1 + t) <= ld(b0 + d - t));
+            i = ok ? t : i;
+        }
+        uint32_t pa = (uint32_t)(a0 + i), pb = (uint32_t)(b0 + d - i);   // heads
+        U a = ld(pa), b = ld(pb);
+        if constexpr (sizeof(U) == 4) {
+            // One output in eight VALU instructions: the compare's carry bit
+            // advances B's head (add with carry) or A's (subtract with
+            // borrow of -1), then both padded addresses.  ALU only; the
+            // loads stay with the compiler.  The compiler's own form of this
+            // step takes ten to eleven.  s_nop: wait states before a VALU
+            // reads VCC as a carry right after a VALU wrote it.
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                uint32_t o, xa, xb, t1, t2;
+                uint64_t c;
+                asm("v_cmp_lt_u32 vcc, %[b], %[a]\n\t"
+                    "v_min_u32 %[o], %[b], %[a]\n\t"
+                    "s_nop 1\n\t"
+                    "v_addc_co_u32_e64 %[pb], %[c], %[pb], 0, vcc\n\t"
+                    "v_subb_co_u32_e64 %[pa], %[c], %[pa], -1, vcc\n\t"
+                    "v_lshrrev_b32 %[t1], 5, %[pa]\n\t"
+                    "v_lshrrev_b32 %[t2], 5, %[pb]\n\t"
+                    "v_add_lshl_u32 %[xa], %[pa], %[t1], 2\n\t"
+                    "v_add_lshl_u32 %[xb], %[pb], %[t2], 2"
+                    : [o] "=&v"(o), [pa] "+v"(pa), [pb] "+v"(pb), [xa] "=&v"(xa), [xb] "=&v"(xb), [t1] "=&v"(t1),
+                      [t2] "=&v"(t2), [c] "=&s"(c)
+                    : [a] "v"(a), [b] "v"(b)
+                    : "vcc");
+                v[r] = o;
+                if (r + 1 < IT) {
+                    a = *(LU*)(kb + xa);
+                    b = *(LU*)(kb + xb);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < IT; ++r) {
+                const bool tb = b < a;
+                v[r] = tb ? b : a;
+                pa += tb ? 0u : 1u;
+                pb += tb ? 1u : 0u;
+                if (r + 1 < IT) {
+                    a = ld(pa);
+                    b = ld(pb);
+                }
+            }
+        }
+    }
+
     static __device__ __forceinline__ void put(Smem& sm, int tid, const E (&v)[IT]) {
 #pragma unroll
         for (int r = 0; r < IT; ++r) {
@@ -168,6 +281,12 @@ struct TileSort {
     // the NEAR test of the general plan.
     static __device__ void run(Smem& sm, const S* src, S* dst, const uint32_t* psrc, uint32_t* pdst, int valid,
                                unsigned long long* desc = nullptr) {
+        body(sm, src, dst, psrc, pdst, valid, desc);
+    }
+    // run() inlined, for a launch's main call site: the LDS array's address
+    // is then a constant that folds into the instructions' offsets.
+    static __device__ __forceinline__ void body(Smem& sm, const S* src, S* dst, const uint32_t* psrc,
+                                                uint32_t* pdst, int valid, unsigned long long* desc = nullptr) {
         const int tid = threadIdx.x;
         E v[IT];
         const bool vec = valid == T && aligned16(src) && (!PAIRS || aligned16(psrc));
@@ -192,7 +311,16 @@ struct TileSort {
 
         wave_sort(v);
 
-        if constexpr (T > kWave * IT) {
+        if constexpr (!PAIRS) {
+            put_k(sm, kWave * IT, tid, v);
+#pragma unroll 1
+            for (int width = kWave * IT; width < T; width *= 2) {
+                __syncthreads();
+                lds_level_k(sm, width, tid, v);
+                __syncthreads();
+                put_k(sm, 2 * width, tid, v);
+            }
+        } else if constexpr (T > kWave * IT) {
             put(sm, tid, v);
 #pragma unroll 1
             for (int width = kWave * IT; width < T; width *= 2) {
@@ -206,10 +334,12 @@ struct TileSort {
         }
         __syncthreads();
 
+        // position of sorted element e in LDS
+        auto at = [](int e) { return PAIRS ? pad(e) : pad(G + e); };
         if (desc != nullptr && tid < 4) {
             constexpr int H = T / 2;
             const int pos = tid == 0 ? 0 : tid == 1 ? valid - 1 : tid == 2 ? H - 1 : H;
-            if (tid < 2 || valid > H) desc[tid] = (unsigned long long)sm.k[pad(pos)];
+            if (tid < 2 || valid > H) desc[tid] = (unsigned long long)sm.k[at(pos)];
         }
         // store, striped so that consecutive lanes write consecutive addresses
         const bool vout = valid == T && aligned16(dst);
@@ -219,11 +349,11 @@ struct TileSort {
                 const int e0 = (tid + q * WG) * VN;
                 V16<S> x;
 #pragma unroll
-                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[pad(e0 + j)]);
+                for (int j = 0; j < VN; ++j) x.v[j] = C::dec(sm.k[at(e0 + j)]);
                 reinterpret_cast<V16<S>*>(dst)[tid + q * WG] = x;
             }
         } else {
-            for (int e = tid; e < valid; e += WG) dst[e] = C::dec(sm.k[pad(e)]);
+            for (int e = tid; e < valid; e += WG) dst[e] = C::dec(sm.k[at(e)]);
         }
         if constexpr (PAIRS) {
             for (int e = tid; e < valid; e += WG) pdst[e] = sm.pay[sm.p[pad(e)]];
