@@ -881,6 +881,55 @@ __device__ __forceinline__ int few_bucket(const U* sp, int ns, U u) {
     return (lo < ns && sp[lo] == u) ? 2 * lo + 1 : 2 * lo;
 }
 
+// Position of sample j of S over [0, n): a point inside stratum j drawn by a
+// hash of j, so that inputs with a period dividing the stratum width (teeth
+// whose length is a multiple of n/S) do not show the sample a few values
+// repeated.
+__device__ __forceinline__ int64_t strat_pos(int64_t j, int64_t n, int64_t S) {
+    const int64_t lo = j * n / S, hi = (j + 1) * n / S;
+    uint32_t h = (uint32_t)j * 0x9E3779B1u;
+    h ^= h >> 15;
+    h *= 0x85EBCA77u;
+    h ^= h >> 13;
+    return hi > lo ? lo + (int64_t)(((uint64_t)h * (uint64_t)(hi - lo)) >> 32) : lo;
+}
+
+// The between keys of a classify tile (bm[r]: wavefront ballot of the keys
+// x[r] that fall between splitters) to S1[n-1-m, ...), in any order: one
+// reservation per tile, and no stores once the job holds more than n/4 of
+// them -- the plan then falls back to GENERAL and never reads them, so a
+// wrong few-unique guess costs one counting read.  Every thread calls it.
+template <class S, int R>
+__device__ __forceinline__ void few_between(const S (&x)[R], const unsigned long long (&bm)[R], int64_t n,
+                                            Ctl* ctl, S* s1) {
+    __shared__ unsigned int s_wc[kClsWG / kWave];
+    __shared__ unsigned long long s_base;
+    const int lane = (int)__lane_id();
+    const int wave = (int)threadIdx.x / kWave;
+    unsigned int c = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) c += (unsigned int)__builtin_popcountll(bm[r]);
+    if (lane == 0) s_wc[wave] = c;
+    __syncthreads();
+    unsigned int tot = 0, before = 0;
+#pragma unroll
+    for (int w = 0; w < kClsWG / kWave; ++w) {
+        before += w < wave ? s_wc[w] : 0u;
+        tot += s_wc[w];
+    }
+    if (threadIdx.x == 0) s_base = tot != 0u ? atomicAdd(&ctl->m, (unsigned long long)tot) : 0ull;
+    __syncthreads();
+    const unsigned long long base = s_base;
+    if ((base + tot) * 4ull > (unsigned long long)n) return;
+    unsigned long long off = base + before;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if ((bm[r] >> lane) & 1ull) s1[n - 1 - (int64_t)(off + __builtin_popcountll(bm[r] & below))] = x[r];
+        off += (unsigned long long)__builtin_popcountll(bm[r]);
+    }
+}
+
 // Bucket counts and between keys of the 4096-key tile [c0, c1) (256 threads).
 template <class C>
 __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int64_t c1, Ctl* ctl, FewTable* ft,
@@ -890,7 +939,6 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
     __shared__ U sp[kFewMax];
     __shared__ unsigned int hist[kFewBuckets];
     const int tid = threadIdx.x;
-    const int lane = (int)__lane_id();
     const int ns = (int)ft->ns;
     const int nb = 2 * ns + 1;
     for (int i = tid; i < ns; i += kClsWG) sp[i] = (U)ft->split[i];
@@ -902,6 +950,7 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
         if (q < c1) x[r] = keys[q];
     }
     __syncthreads();
+    unsigned long long bm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t q = c0 + r * kClsWG + tid;
@@ -911,22 +960,13 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
             atomicAdd(&hist[b], 1u);
             between = (b & 1) == 0;
         }
-        const unsigned long long mask = __builtin_amdgcn_ballot_w64(between);
-        if (mask != 0ull) {
-            const int leader = __builtin_ctzll(mask);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&ctl->m, (unsigned long long)__builtin_popcountll(mask));
-            base = __shfl(base, leader);
-            if (between) {
-                const unsigned long long rank = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-                s1[n - 1 - (int64_t)(base + rank)] = x[r];
-            }
-        }
+        bm[r] = __builtin_amdgcn_ballot_w64(between);
     }
     __syncthreads();
     unsigned long long* cc = ft->cnt[blockIdx.x % kFewCopies];
     for (int b = tid; b < nb; b += kClsWG)
         if (hist[b] != 0u) atomicAdd(&cc[b], (unsigned long long)hist[b]);
+    few_between<typename C::S, R>(x, bm, n, ctl, s1);
 }
 
 // Bucket totals (the counter copies summed, one bucket per thread), then
@@ -1059,7 +1099,6 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
     constexpr int R = kClsTC / kClsWG;
     static_assert(kClsTC < 65536, "16-bit tile counters");
     const int tid = threadIdx.x;
-    const int lane = (int)__lane_id();
     const int ns = (int)fw->ns;
     const int nb = 2 * ns + 1;
     int P = 1;
@@ -1073,6 +1112,7 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
         if (q < c1) x[r] = keys[q];
     }
     __syncthreads();
+    unsigned long long bm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t q = c0 + r * kClsWG + tid;
@@ -1084,17 +1124,7 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
             atomicAdd(&fl.hist[b >> 1], 1u << ((b & 1) * 16));
             between = (b & 1) == 0;
         }
-        const unsigned long long mask = __builtin_amdgcn_ballot_w64(between);
-        if (mask != 0ull) {
-            const int leader = __builtin_ctzll(mask);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&ctl->m, (unsigned long long)__builtin_popcountll(mask));
-            base = __shfl(base, leader);
-            if (between) {
-                const unsigned long long rank = __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-                s1[n - 1 - (int64_t)(base + rank)] = x[r];
-            }
-        }
+        bm[r] = __builtin_amdgcn_ballot_w64(between);
     }
     __syncthreads();
     for (int w = tid; w < (nb + 1) / 2; w += kClsWG) {
@@ -1102,6 +1132,7 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
         if (h & 0xFFFFu) atomicAdd(&fw->cnt[2 * w], (unsigned long long)(h & 0xFFFFu));
         if ((h >> 16) != 0u && 2 * w + 1 < nb) atomicAdd(&fw->cnt[2 * w + 1], (unsigned long long)(h >> 16));
     }
+    few_between<typename C::S, R>(x, bm, n, ctl, s1);
 }
 
 // Offsets (a scan across the verify workgroup, kWideBuckets / kVerWG buckets
@@ -1477,7 +1508,6 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     if (tid < 2) s_flag[tid] = s_both[tid] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
-    const int64_t ntiles = (n + kClsTC - 1) / kClsTC;
     const int64_t c0 = t * kClsTC;
     const int64_t c1 = (c0 + kClsTC) < n ? (c0 + kClsTC) : n;
     const int64_t w0 = c0 - kClsH > 0 ? c0 - kClsH : 0;
@@ -2176,7 +2206,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             }
             U sv[PER];
 #pragma unroll
-            for (int r = 0; r < PER; ++r) sv[r] = C::enc(keys[(int64_t)(tid * PER + r) * n / kFewSample]);
+            for (int r = 0; r < PER; ++r) sv[r] = C::enc(keys[strat_pos(tid * PER + r, n, kFewSample)]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
@@ -2213,7 +2243,10 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                     if (lane < total) ft->split[lane] = (unsigned long long)v[0];
                 }
                 ns = total;
-            } else if (fw != nullptr) {
+            } else if (fw != nullptr && total <= kFewSample * 15 / 16) {
+                // (more than 960 distinct values among 1024 samples: the
+                // array holds far more than kWideMax values -- 4096 values,
+                // however their frequencies, show at most about 906 +- 9)
                 // wide: kWideSample keys in rounds of WB per thread into a
                 // larger hash set of codes (code + 1, as above), until more
                 // than kWideMax distinct ones are seen; a round starts only
@@ -2235,7 +2268,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
                     U sv2[WB];
 #pragma unroll
                     for (int r = 0; r < WB; ++r)
-                        sv2[r] = C::enc(keys[(int64_t)(tid * PERW + b0 + r) * n / kWideSample]);
+                        sv2[r] = C::enc(keys[strat_pos(tid * PERW + b0 + r, n, kWideSample)]);
 #pragma unroll
                     for (int r = 0; r < WB; ++r) {
                         const U code = (U)(sv2[r] + (U)1);
@@ -2277,7 +2310,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             if (ns < 0 && total > kFewMax && s_force) {
                 __shared__ int s_cnt[kProbeWG / kWave];
                 S* samp = reinterpret_cast<S*>(ft->sample);
-                for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[(int64_t)i * n / kFewSample];
+                for (int i = tid; i < kFewSample; i += kProbeWG) samp[i] = keys[strat_pos(i, n, kFewSample)];
                 __syncthreads();
                 FS::run(few_lds.fsm, samp, samp, nullptr, nullptr, kFewSample);
                 __syncthreads();

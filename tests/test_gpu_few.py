@@ -214,3 +214,26 @@ def test_wide_between_keys(gpu, n, frac):
     st = check(gpu, a)
     if n >= 1_000_000:
         assert st["path"] == "few" and st["outliers"] > 0, st
+
+
+@pytest.mark.parametrize("k", [32, 128, 256])
+def test_periodic_input_does_not_alias_the_sample(gpu, k):
+    """k-even teeth at 2,000,000 keys: the tooth length is a multiple of the
+    sample strata's width for these k, so evenly spaced samples saw a few
+    hundred values of the 7,813..62,500 present and sent the sort into the
+    bucket pass, which then fell back after a counting read whose between
+    keys all went through one atomic counter (383 us of classify for
+    k = 128).  Samples drawn inside their strata see the real spread; the
+    classify launch stays a no-op or a run scan."""
+    n = 2_000_000
+    a = inputs.class_int32("even_teeth", n, k, seed=k)
+    check(gpu, a)
+    gpu.set_option("profile", 1)
+    try:
+        gpu.profile_collect("")
+        for _ in range(3):
+            gpu_sort_keys(gpu, a, "int32")
+        cnt, ms = gpu.profile_collect("classify")
+    finally:
+        gpu.set_option("profile", 0)
+    assert cnt == 3 and ms / cnt < 0.1, (cnt, ms)
