@@ -66,11 +66,14 @@ typedef enum {
                               place, disordered tiles sorted, runs whose values are
                               already in order joined, then a merge tree over the
                               remaining leaves (Sec. 3 natural runs, Sec. 2 Mono) */
-    SR_PATH_FEW = 5,       /* few distinct keys (keys only): equal buckets around at
-                              most 4096 sampled values -- the GPU form of 3-way
-                              partitioning (Sec. 4, k-limited of Sec. 2, Table 1's
-                              12-limited few-unique type); keys between the
-                              sampled values are sorted separately */
+    SR_PATH_FEW = 5,       /* few distinct keys: equal buckets around at most 4096
+                              sampled values -- the GPU form of 3-way partitioning
+                              (Sec. 4, k-limited of Sec. 2, Table 1's 12-limited
+                              few-unique type); keys between the sampled values
+                              are sorted separately.  Pairs: at most 64 values,
+                              every key equal to one of them, n <= 4,194,304;
+                              each key and payload is placed in input order among
+                              its equals (stable) */
     SR_PATH_NEAR = 6       /* tile sort, then two rounds of neighbour merges: tile
                               pairs (0,1),(2,3),... and then (1,2),(3,4),...; taken
                               when the sorted tiles show that every tile overlaps
@@ -325,7 +328,7 @@ const char *sr_last_error_message(void);
  *                 path launches (on the caller's stream); 0 = off (default).
  *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
- *   "few_path"    1 = keys-only sorts may take SR_PATH_FEW (default); 0 = never.
+ *   "few_path"    1 = sorts may take SR_PATH_FEW (default); 0 = never.
  *                 A forced SR_PATH_FEW still falls back to SR_PATH_GENERAL when
  *                 more than a quarter of the keys miss the sampled values.
  *   "near_path"   1 = general sorts may finish as SR_PATH_NEAR when their

@@ -1050,6 +1050,159 @@ __device__ __forceinline__ void few_place(typename C::S* U, const typename C::S*
     }
 }
 
+// ------------------------------------------------------ few unique, pairs
+// FEW for key + payload sorts, when every key equals one of at most kFewMax
+// sampled values (no keys between them; otherwise the plan falls back to
+// GENERAL with U untouched) and the per-tile counts fit the wide table's
+// space (n <= 1024 tiles of kClsTC keys).  Equal keys must keep their input
+// order, so each (value, tile) gets its own output range:
+//   classify  tile t's count of each value into row i, column t of a count
+//             matrix; keys between values only counted (into m)
+//   verify    each value's row scanned (exclusive, in place; one thread per
+//             value), the values' output offsets; GENERAL unless m == 0 and
+//             the counts add up to n
+//   scatter   tile t again, in input order (16 rounds of 256 keys): a key's
+//             rank among the tile's earlier keys of its value (wave ballots
+//             per value present, then the earlier waves' counts and the
+//             earlier rounds') gives its output position; key and payload
+//             go to S1 / PS1 there
+//   merge slot 0: S1 / PS1 copied back to U / PU
+// One read of the keys, one read and one write of keys and payloads, one
+// copy: stable by construction.
+
+// Counts of the kClsTC-key tile t = [c0, c1) (256 threads).
+template <class C>
+__device__ void few_count_pairs(const typename C::S* keys, int64_t c0, int64_t c1, Ctl* ctl, const FewTable* ft,
+                                unsigned int* fewm, int64_t t, int64_t ncls) {
+    using U = typename C::U;
+    constexpr int R = kClsTC / kClsWG;
+    __shared__ U sp[kFewMax];
+    __shared__ unsigned int hist[kFewMax];
+    __shared__ unsigned int s_between;
+    const int tid = threadIdx.x;
+    const int ns = (int)ft->ns;
+    for (int i = tid; i < ns; i += kClsWG) {
+        sp[i] = (U)ft->split[i];
+        hist[i] = 0u;
+    }
+    if (tid == 0) s_between = 0u;
+    __syncthreads();
+    unsigned int nb = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + r * kClsWG + tid;
+        if (q < c1) {
+            const int b = few_bucket<U>(sp, ns, C::enc(keys[q]));
+            if (b & 1) atomicAdd(&hist[b >> 1], 1u);
+            else ++nb;
+        }
+    }
+    if (nb != 0u) atomicAdd(&s_between, nb);
+    __syncthreads();
+    for (int i = tid; i < ns; i += kClsWG) fewm[(int64_t)i * ncls + t] = hist[i];
+    if (tid == 0 && s_between != 0u) atomicAdd(&ctl->m, (unsigned long long)s_between);
+}
+
+// Row scans and value offsets (the verify workgroup).
+__device__ void few_plan_pairs(Ctl* ctl, int64_t n, FewTable* ft, unsigned int* fewm, int64_t ncls) {
+    __shared__ unsigned long long s_tot[kFewMax];
+    const int ns = (int)ft->ns;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+        unsigned int* row = fewm + (int64_t)i * ncls;
+        unsigned long long run = 0;
+        for (int64_t t = 0; t < ncls; ++t) {
+            const unsigned int c = row[t];
+            row[t] = (unsigned int)run;
+            run += c;
+        }
+        s_tot[i] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const unsigned long long m = ld_agent(&ctl->m);
+    long long o = 0;
+    for (int i = 0; i < ns; ++i) {
+        ft->off[2 * i + 1] = o;
+        o += (long long)s_tot[i];
+    }
+    if (m != 0ull || o != n) {
+        ctl->path = SR_PATH_GENERAL;
+        ctl->m = 0;
+    }
+    ctl->job_passes = 0;
+}
+
+// Scatter of tile t (256 threads): keys and payloads to their places in
+// S1 / PS1.
+template <class C>
+__device__ void few_scatter_pairs(const typename C::S* keys, const uint32_t* pay, typename C::S* s1, uint32_t* ps1,
+                                  int64_t n, const FewTable* ft, const unsigned int* fewm, int64_t t,
+                                  int64_t ncls) {
+    using U = typename C::U;
+    using S = typename C::S;
+    constexpr int R = kClsTC / kClsWG;
+    constexpr int NW = kClsWG / kWave;
+    __shared__ U sp[kFewMax];
+    __shared__ long long base[kFewMax];            // place of the tile's next key of each value
+    __shared__ unsigned int wcnt[NW][kFewMax];     // keys of each value per wave, this round
+    const int tid = threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int wave = tid / kWave;
+    const int64_t c0 = t * kClsTC;
+    const int64_t c1 = (c0 + kClsTC) < n ? (c0 + kClsTC) : n;
+    const int ns = (int)ft->ns;
+    for (int i = tid; i < ns; i += kClsWG) {
+        sp[i] = (U)ft->split[i];
+        base[i] = ft->off[2 * i + 1] + (long long)fewm[(int64_t)i * ncls + t];
+    }
+    for (int i = tid; i < NW * kFewMax; i += kClsWG) wcnt[i / kFewMax][i % kFewMax] = 0u;
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = 0; r < R; ++r) {
+        const int64_t q = c0 + (int64_t)r * kClsWG + tid;
+        int b = -1;  // value index; -1: no key, or a key between values (none in a FEW plan)
+        S x{};
+        uint32_t p = 0;
+        if (q < c1) {
+            x = keys[q];
+            p = pay[q];
+            const int bb = few_bucket<U>(sp, ns, C::enc(x));
+            b = (bb & 1) ? (bb >> 1) : -1;
+        }
+        // one round per value present in the wavefront: its lanes' ranks,
+        // and its count from its first lane
+        unsigned long long rem = __builtin_amdgcn_ballot_w64(b >= 0);
+        int rank = 0;
+        while (rem != 0ull) {
+            const int lead = __builtin_ctzll(rem);
+            const int bl = __shfl(b, lead);
+            const unsigned long long mk = __builtin_amdgcn_ballot_w64(b == bl);
+            if (b == bl) rank = __builtin_popcountll(mk & below);
+            if (lane == lead) wcnt[wave][bl] = (unsigned int)__builtin_popcountll(mk);
+            rem &= ~mk;
+        }
+        __syncthreads();
+        if (b >= 0) {
+            long long pos = base[b] + rank;
+            for (int w = 0; w < wave; ++w) pos += (long long)wcnt[w][b];
+            if (pos >= 0 && pos < n) {
+                s1[pos] = x;
+                ps1[pos] = p;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < ns; i += kClsWG) {
+            unsigned int c = 0;
+            for (int w = 0; w < NW; ++w) {
+                c += wcnt[w][i];
+                wcnt[w][i] = 0u;
+            }
+            base[i] += (long long)c;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ wide few unique
 // The FEW job with 65 to 4096 sampled values (Table 1's few-unique type is
 // 12-limited: 4096 values).  Buckets and job are those above; what changes
@@ -1370,7 +1523,13 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
         runs_merge<MC, S>(sm, ra, U, S1, PU, PS1, k);
         return;
     }
-    if constexpr (!PAIRS) {
+    if constexpr (PAIRS) {
+        // FEW of pairs: the placed keys and payloads back into the user buffers
+        if (ctl != nullptr && ft != nullptr && ctl->path == SR_PATH_FEW && k == 0) {
+            copy_part(S1, U, PS1, PU, n, (int64_t)blockIdx.x, (int64_t)gridDim.x);
+            return;
+        }
+    } else {
         if (ctl != nullptr) {
             const int path = ctl->path;
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
@@ -1416,7 +1575,13 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         runs_merge_persist<MC, S>(sm.p.b, ra, U, S1, PU, PS1, k, co);
         return;
     }
-    if constexpr (!PAIRS) {
+    if constexpr (PAIRS) {
+        // FEW of pairs: the placed keys and payloads back into the user buffers
+        if (ctl != nullptr && ft != nullptr && ctl->path == SR_PATH_FEW && k == 0) {
+            copy_part(S1, U, PS1, PU, n, (int64_t)blockIdx.x, (int64_t)gridDim.x);
+            return;
+        }
+    } else {
         if (ctl != nullptr) {
             const int path = ctl->path;
             if (ft != nullptr && path == SR_PATH_FEW && k == ctl->job_passes) {
@@ -1480,7 +1645,7 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
                                                      unsigned int* flags, unsigned long long* tfirst,
                                                      unsigned long long* tlast, unsigned long long* tcount,
                                                      int runs_ok, RunTile* rdesc, FewTable* ft,
-                                                     typename C::S* s1, WideTable* fw) {
+                                                     typename C::S* s1, WideTable* fw, unsigned int* fewm) {
     using U = typename C::U;
     // the outlier window and the wide few-unique tables share the launch's LDS
     __shared__ union {
@@ -1491,7 +1656,8 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
     if (path == SR_PATH_FEW) {
         const int64_t f0 = (int64_t)blockIdx.x * kClsTC;
         const int64_t f1 = (f0 + kClsTC) < n ? (f0 + kClsTC) : n;
-        if (fw != nullptr && ctl->few_wide) wide_count<C>(keys, n, f0, f1, ctl, fw, s1, cls_lds.wide);
+        if (fewm != nullptr) few_count_pairs<C>(keys, f0, f1, ctl, ft, fewm, blockIdx.x, gridDim.x);
+        else if (fw != nullptr && ctl->few_wide) wide_count<C>(keys, n, f0, f1, ctl, fw, s1, cls_lds.wide);
         else few_count<C>(keys, n, f0, f1, ctl, ft, s1);
         return;
     }
@@ -1706,7 +1872,8 @@ template <class C>
 __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t n, const Ctl* ctl,
                                                     typename C::S* s1, const unsigned int* flags,
                                                     const unsigned long long* kpref_t, const RunArea* ra,
-                                                    uint32_t* pay) {
+                                                    uint32_t* pay, uint32_t* spay, const FewTable* ft,
+                                                    const unsigned int* fewm) {
     using S = typename C::S;
     constexpr int CP = kClsTC / kClsWG;
     constexpr int NW = kClsTC / 32;  // mask words per tile
@@ -1714,6 +1881,10 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
     const int path = ctl->path;
     if (path == SR_PATH_RUNS && ra != nullptr) {
         runs_reverse<S>(keys, pay, ra);
+        return;
+    }
+    if (path == SR_PATH_FEW && fewm != nullptr) {
+        few_scatter_pairs<C>(keys, pay, s1, spay, n, ft, fewm, blockIdx.x, gridDim.x);
         return;
     }
     if (path != SR_PATH_OUTLIER) return;
@@ -1783,10 +1954,11 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
                                                    unsigned long long* kpref_t, int64_t T_sort,
                                                    const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
                                                    int runs_ok, int64_t merge_ch, int M, FewTable* ft,
-                                                   WideTable* fw) {
+                                                   WideTable* fw, unsigned int* fewm) {
     const int path0 = ctl->path;
     if (path0 == SR_PATH_FEW) {
-        if (fw != nullptr && ctl->few_wide) wide_plan(ctl, n, fw, T_sort);
+        if (fewm != nullptr) few_plan_pairs(ctl, n, ft, fewm, ntiles);
+        else if (fw != nullptr && ctl->few_wide) wide_plan(ctl, n, fw, T_sort);
         else few_plan(ctl, n, ft, T_sort);
         return;
     }
@@ -2725,7 +2897,7 @@ int g_force_path = -1;
 bool g_profile = false;
 bool g_outlier_enabled = true;  // allow the OUTLIER path for keys-only sorts
 bool g_runs_enabled = true;     // allow the RUNS path for keys-only sorts
-bool g_few_enabled = true;      // allow the FEW path for keys-only sorts
+bool g_few_enabled = true;      // allow the FEW path
 bool g_near_enabled = true;     // allow the NEAR plan on general sorts
 // Launch-shape options; the "auto" value defers to the tuning table, then to
 // the built-in rule in resolve_shape.
@@ -2897,6 +3069,7 @@ struct LastCall {
     int merge_passes = 0;
     int trivial = 1;
     bool fan4 = false;  // general passes were four-way
+    bool pairs = false;
     Ctl* ctl = nullptr;
 };
 
@@ -3171,6 +3344,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     LastCall lc;
     lc.n = n;
     lc.es = (int)sizeof(S) + (PAIRS ? 4 : 0);
+    lc.pairs = PAIRS;
     lc.merge_passes = M;
     if (ntiles == 1) {
         if (prepare_only) return SR_OK;
@@ -3190,7 +3364,10 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     // keys-only sorts and pairs with tiles of whole run-scan tiles (the
     // run reversal of pairs is the stable one)
     const bool runs_ok = g_runs_enabled && T >= kClsTC;
-    const bool few_ok = !PAIRS && g_few_enabled;
+    // pairs: equal buckets only (at most kFewMax values), their count matrix
+    // (kFewMax x tiles of u32) in the wide table's space: n <= 4,194,304
+    const bool few_ok =
+        g_few_enabled && (!PAIRS || (size_t)cdiv(n, kClsTC) * kFewMax * sizeof(unsigned int) <= sizeof(WideTable));
     const bool scan_ok = outlier_ok || runs_ok || few_ok;
     const int64_t ncls = scan_ok ? cdiv(n, kClsTC) : 0;
     LaunchShape sh;
@@ -3255,9 +3432,12 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         near_ok ? reinterpret_cast<unsigned long long*>(static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes +
                                                         rdesc_bytes + rarea_bytes)
                 : nullptr;
-    WideTable* fw = few_ok ? reinterpret_cast<WideTable*>(static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes +
-                                                          rdesc_bytes + rarea_bytes + tdesc_bytes)
-                           : nullptr;
+    void* few_area = few_ok ? static_cast<char*>(ws->aux) + 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes +
+                                  tdesc_bytes
+                            : nullptr;
+    // keys: the wide table; pairs: the count matrix of the pairs FEW job
+    WideTable* fw = PAIRS ? nullptr : reinterpret_cast<WideTable*>(few_area);
+    unsigned int* fewm = PAIRS ? reinterpret_cast<unsigned int*>(few_area) : nullptr;
 
     {
         ProfScope ps(ls, "probe");
@@ -3288,7 +3468,7 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         {
             ProfScope ps(ls, "classify");
             hipLaunchKernelGGL(k_classify<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, (const S*)keys, n, ctl,
-                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc, ftab, skeys, fw);
+                               flags, tfirst, tlast, tcount, runs_ok ? 1 : 0, rdesc, ftab, skeys, fw, fewm);
             SR_LAUNCH_CHECK("classify");
         }
         {
@@ -3296,13 +3476,13 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
             hipLaunchKernelGGL(k_verify<C>, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
                                (const unsigned long long*)tcount, kpref_t, (int64_t)T, (const S*)keys,
-                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab, fw);
+                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab, fw, fewm);
             SR_LAUNCH_CHECK("verify");
         }
         ProfScope ps(ls, "scatter");
         hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, keys, n, (const Ctl*)ctl, skeys,
                            (const unsigned int*)flags, (const unsigned long long*)kpref_t, (const RunArea*)rarea,
-                           PAIRS ? pay : nullptr);
+                           PAIRS ? pay : nullptr, spay, (const FewTable*)ftab, (const unsigned int*)fewm);
         SR_LAUNCH_CHECK("scatter");
     }
     {
@@ -3924,12 +4104,14 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
             break;
         }
         case SR_PATH_FEW: {
-            // bucket count (n read, m written) + sort of the m between keys
-            // + fill (n written, m read)
+            // keys: bucket count (n read, m written) + sort of the m between
+            // keys + fill (n written, m read); pairs (m = 0): count (keys
+            // read) + placement (n read, n written) + copy back
             const double m = (double)h.m;
             out->outliers = (int64_t)h.m;
             out->merge_passes = h.job_passes + 1;
-            eq = 1.0 + (2.0 + h.job_passes) * m / (double)lc.n;
+            eq = lc.pairs ? 2.0 + 0.5 * (double)(lc.es - 4) / (double)lc.es
+                          : 1.0 + (2.0 + h.job_passes) * m / (double)lc.n;
             break;
         }
         case SR_PATH_NEAR:

@@ -2,8 +2,9 @@
 
 Few-unique inputs (the Table 1 type and the k-limited class of Sec. 2),
 with and without keys that the probe's sample misses (they go through the
-separate between-key sort), float32 specials and uint64 keys.  Every result
-is compared bit for bit with the oracle; paths are checked against design
+separate between-key sort), float32 specials and uint64 keys; key + payload
+sorts, whose equal keys must keep their input order.  Every result is
+compared bit for bit with the oracle; paths are checked against design
 invariants.
 """
 import numpy as np
@@ -237,3 +238,86 @@ def test_periodic_input_does_not_alias_the_sample(gpu, k):
     finally:
         gpu.set_option("profile", 0)
     assert cnt == 3 and ms / cnt < 0.1, (cnt, ms)
+
+
+# ------------------------------------------------------------------ pairs
+
+from test_gpu_sort import gpu_sort_pairs  # noqa: E402
+
+
+def check_pairs(gpu, k, dtype="int32", p=None):
+    """Pairs against the oracle's stable sort; the payload is the input
+    position unless given, so any reordering of equal keys shows."""
+    if p is None:
+        p = np.arange(k.size, dtype=np.uint32)
+    gk, gp = gpu_sort_pairs(gpu, k, p, dtype)
+    wk, wp = oracle.sort_pairs(k, p)
+    assert np.array_equal(bits(gk), bits(wk)) and np.array_equal(gp, wp)
+    return gpu.last_stats()
+
+
+@pytest.mark.parametrize("n", [8_193, 20_000, 300_001, 2_000_000, 4_194_304])
+def test_pairs_few_unique(gpu, n):
+    a = inputs.few_unique_int32(n, seed=n)
+    st = check_pairs(gpu, a)
+    assert st["path"] == "few" and st["outliers"] == 0, st
+
+
+def test_pairs_few_size_limit(gpu):
+    """The count matrix holds 1024 tiles of 4096 keys: one key more and the
+    pairs take the general path, exactly."""
+    n = 4_194_305
+    st = check_pairs(gpu, inputs.few_unique_int32(n, seed=3))
+    assert st["path"] != "few", st
+
+
+@pytest.mark.parametrize("n,frac", [(300_001, 0.001), (2_000_000, 0.0001), (2_000_000, 0.2)])
+def test_pairs_between_keys_fall_back(gpu, n, frac):
+    """Keys between the sampled values: the pairs plan needs none, so it
+    turns back into GENERAL before touching the arrays."""
+    rng = np.random.default_rng(int(n * frac * 1e4) % 2**32)
+    vals = rng.integers(-2**31, 2**31, size=20, dtype=np.int64)
+    a = vals[rng.integers(0, 20, size=n)]
+    other = rng.random(n) < frac
+    a[other] = rng.integers(-2**31, 2**31, size=int(other.sum()), dtype=np.int64)
+    st = check_pairs(gpu, a.astype(np.int32))
+    assert st["path"] != "few", st
+
+
+@pytest.mark.parametrize("distinct,few", [(2, True), (64, True), (65, False)])
+def test_pairs_value_count(gpu, distinct, few):
+    n = 1_000_003
+    rng = np.random.default_rng(distinct + 100)
+    vals = np.unique(rng.integers(-2**31, 2**31, size=4 * distinct, dtype=np.int64))[:distinct]
+    a = vals[rng.integers(0, distinct, size=n)].astype(np.int32)
+    p = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)  # payloads not positions
+    st = check_pairs(gpu, a, p=p)
+    assert (st["path"] == "few") == few, st
+
+
+def test_pairs_few_other_dtypes(gpu):
+    n = 1_500_007
+    rng = np.random.default_rng(77)
+    pool = np.array([0x7FC00000, 0xFFC00000, 0x80000000, 0x00000000, 0x7F800000, 0xFF800000, 0x3F800000],
+                    dtype=np.uint32).view(np.float32)
+    f = pool[rng.integers(0, pool.size, size=n)]
+    assert check_pairs(gpu, f, "float32")["path"] == "few"
+    vals = np.array([0, 2**64 - 1, 5, 2**63, 77, 2**40 + 3], dtype=np.uint64)
+    u = vals[rng.integers(0, vals.size, size=n)]
+    assert check_pairs(gpu, u, "uint64")["path"] == "few"
+
+
+def test_pairs_few_switched_off_and_forced(gpu):
+    a = inputs.few_unique_int32(500_000, seed=8)
+    gpu.set_option("few_path", 0)
+    try:
+        assert check_pairs(gpu, a)["path"] != "few"
+    finally:
+        gpu.set_option("few_path", 1)
+    gpu.set_option("force_path", 5)
+    try:
+        assert check_pairs(gpu, a)["path"] == "few"
+        r = inputs.random_int32(300_001, seed=9)
+        assert check_pairs(gpu, r)["path"] == "general"   # forced, then turned back
+    finally:
+        gpu.set_option("force_path", -1)
