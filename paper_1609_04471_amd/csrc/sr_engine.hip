@@ -930,14 +930,22 @@ __device__ __forceinline__ void few_between(const S (&x)[R], const unsigned long
     }
 }
 
+// LDS of the small-table counts (shares the classify launch's union).
+template <class U>
+struct FewLds {
+    U sp[kFewMax];
+    unsigned int hist[kFewBuckets];
+    unsigned int between;
+};
+
 // Bucket counts and between keys of the 4096-key tile [c0, c1) (256 threads).
 template <class C>
 __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int64_t c1, Ctl* ctl, FewTable* ft,
-                          typename C::S* s1) {
+                          typename C::S* s1, FewLds<typename C::U>& fl) {
     using U = typename C::U;
     constexpr int R = kClsTC / kClsWG;
-    __shared__ U sp[kFewMax];
-    __shared__ unsigned int hist[kFewBuckets];
+    U* sp = fl.sp;
+    unsigned int* hist = fl.hist;
     const int tid = threadIdx.x;
     const int ns = (int)ft->ns;
     const int nb = 2 * ns + 1;
@@ -1073,12 +1081,12 @@ __device__ __forceinline__ void few_place(typename C::S* U, const typename C::S*
 // Counts of the kClsTC-key tile t = [c0, c1) (256 threads).
 template <class C>
 __device__ void few_count_pairs(const typename C::S* keys, int64_t c0, int64_t c1, Ctl* ctl, const FewTable* ft,
-                                unsigned int* fewm, int64_t t, int64_t ncls) {
+                                unsigned int* fewm, int64_t t, int64_t ncls, FewLds<typename C::U>& fl) {
     using U = typename C::U;
     constexpr int R = kClsTC / kClsWG;
-    __shared__ U sp[kFewMax];
-    __shared__ unsigned int hist[kFewMax];
-    __shared__ unsigned int s_between;
+    U* sp = fl.sp;
+    unsigned int* hist = fl.hist;
+    unsigned int& s_between = fl.between;
     const int tid = threadIdx.x;
     const int ns = (int)ft->ns;
     for (int i = tid; i < ns; i += kClsWG) {
@@ -1229,19 +1237,35 @@ struct WideTable {
     unsigned long long sample[kWideMax];     // the probe's distinct samples (raw keys), sorted in place
 };
 
-// Splitters below code u: binary search over sp[0, P) without branches (P a
-// power of two; entries past the splitters hold the largest code).
+// Splitters below code u: binary search over the ns (>= 1) splitter codes
+// sp[] without branches (P >= ns a power of two; positions past the
+// splitters count as the largest code, their reads clamped to the last).
+// The steps of at least Q = max(P / kWideIdx, 1) positions read idx[] in LDS
+// (every Q-th splitter), the last log2(Q) steps read the table through the cache:
+// a copy of the whole table in LDS (16 KB) halved the classify launch's
+// occupancy on the outlier path, whose window shares that LDS.
+constexpr int kWideIdx = 256;
 template <class U>
-__device__ __forceinline__ int wide_below(const U* sp, int P, U u) {
+__device__ __forceinline__ int wide_below(const unsigned long long* sp, const U* idx, int ns, int P, U u) {
+    const int Q = P > kWideIdx ? P / kWideIdx : 1;
     int base = 0;
-    for (int half = P >> 1; half > 0; half >>= 1) base = sp[base + half] < u ? base + half : base;
-    return base + (sp[base] < u ? 1 : 0);
+    int half = P >> 1;
+    for (; half >= Q && half > 0; half >>= 1) {
+        const int j = base + half;
+        base = idx[j / Q] < u ? j : base;
+    }
+    for (; half > 0; half >>= 1) {
+        const int j = base + half;
+        const U y = (U)sp[j < ns ? j : ns - 1];
+        base = (j < ns && y < u) ? j : base;
+    }
+    return base + ((U)sp[base] < u ? 1 : 0);
 }
 
 template <class U>
 struct WideLds {
-    U sp[kWideMax];                              // splitter codes, padded with the largest code
     unsigned int hist[(kWideBuckets + 1) / 2];   // two 16-bit counters per word
+    U idx[kWideIdx];                             // every (P / kWideIdx)-th splitter code
 };
 
 // Bucket counts and between keys of the 4096-key tile [c0, c1) (256 threads).
@@ -1256,8 +1280,13 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
     const int nb = 2 * ns + 1;
     int P = 1;
     while (P < ns) P <<= 1;
-    for (int i = tid; i < P; i += kClsWG) fl.sp[i] = i < ns ? (U)fw->split[i] : (U)~(U)0;
+    const unsigned long long* sp = fw->split;
     for (int w = tid; w < (nb + 1) / 2; w += kClsWG) fl.hist[w] = 0u;
+    static_assert(kWideIdx <= kClsWG && kWideMax / kWideIdx >= 1, "one index entry per thread");
+    if (tid < kWideIdx) {
+        const int j = tid * (P > kWideIdx ? P / kWideIdx : 1);
+        fl.idx[tid] = j < ns ? (U)sp[j] : (U)~(U)0;
+    }
     typename C::S x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1272,8 +1301,8 @@ __device__ void wide_count(const typename C::S* keys, int64_t n, int64_t c0, int
         bool between = false;
         if (q < c1) {
             const U u = C::enc(x[r]);
-            const int lo = wide_below<U>(fl.sp, P, u);
-            const int b = (lo < ns && fl.sp[lo] == u) ? 2 * lo + 1 : 2 * lo;
+            const int lo = wide_below<U>(sp, fl.idx, ns, P, u);
+            const int b = (lo < ns && (U)sp[lo < ns ? lo : ns - 1] == u) ? 2 * lo + 1 : 2 * lo;
             atomicAdd(&fl.hist[b >> 1], 1u << ((b & 1) * 16));
             between = (b & 1) == 0;
         }
@@ -1647,18 +1676,19 @@ __global__ __launch_bounds__(kClsWG) void k_classify(const typename C::S* keys, 
                                                      int runs_ok, RunTile* rdesc, FewTable* ft,
                                                      typename C::S* s1, WideTable* fw, unsigned int* fewm) {
     using U = typename C::U;
-    // the outlier window and the wide few-unique tables share the launch's LDS
+    // the outlier window and the few-unique counters share the launch's LDS
     __shared__ union {
         U sk[kClsW];
         WideLds<U> wide;
+        FewLds<U> few;
     } cls_lds;
     const int path = ctl->path;
     if (path == SR_PATH_FEW) {
         const int64_t f0 = (int64_t)blockIdx.x * kClsTC;
         const int64_t f1 = (f0 + kClsTC) < n ? (f0 + kClsTC) : n;
-        if (fewm != nullptr) few_count_pairs<C>(keys, f0, f1, ctl, ft, fewm, blockIdx.x, gridDim.x);
+        if (fewm != nullptr) few_count_pairs<C>(keys, f0, f1, ctl, ft, fewm, blockIdx.x, gridDim.x, cls_lds.few);
         else if (fw != nullptr && ctl->few_wide) wide_count<C>(keys, n, f0, f1, ctl, fw, s1, cls_lds.wide);
-        else few_count<C>(keys, n, f0, f1, ctl, ft, s1);
+        else few_count<C>(keys, n, f0, f1, ctl, ft, s1, cls_lds.few);
         return;
     }
     const bool do_runs = runs_ok && (path == SR_PATH_RUNS || (path == SR_PATH_OUTLIER && ctl->dual));
