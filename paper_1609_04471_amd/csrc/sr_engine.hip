@@ -1211,6 +1211,133 @@ __device__ void few_scatter_pairs(const typename C::S* keys, const uint32_t* pay
     }
 }
 
+// ---------------------------------------------------- outliers, pairs
+// OUTLIER for key + payload sorts.  The kept keys are in input order and
+// sorted; an outlier and a kept key with the same key must come out in input
+// order, which the keys alone do not tell.  The scatter stores the outliers
+// in input order, each with its index j as the payload that the outlier sort
+// carries (stable: equal outliers keep their order), and beside the job its
+// payload and its kept-before count kb_j (the kept keys ahead of it in the
+// input).  Then, with A the kept keys and [lo, hi) the range of A equal to
+// an outlier's key, the sorted outlier k goes to k + clamp(kb_j, lo, hi)
+// (merge slot P), and the kept key a to the a-th position left free (slot
+// P + 1).  The job is taken for m <= n/4 and P + 2 <= M merge slots.
+
+// First index of A[0, na) whose code is not below u (strict: above u).
+template <class C, bool STRICT>
+__device__ __forceinline__ int64_t bound_in(const typename C::S* A, int64_t na, typename C::U u) {
+    int64_t lo = 0, hi = na;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const typename C::U y = C::enc(A[mid]);
+        if (STRICT ? y <= u : y < u) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Merge slot P: every sorted outlier k to its place in U / PU; its place is
+// kept in PS1[n-m+k] (sorted: the places increase with k) for slot P + 1.
+template <class C>
+__device__ void outlier_place_pairs(typename C::S* Ub, const typename C::S* S1, uint32_t* PUb, uint32_t* PS1,
+                                    int64_t n, int64_t m, const uint32_t* opay, const uint32_t* okb) {
+    using S = typename C::S;
+    const int64_t na = n - m;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+        const S x = S1[na + k];
+        const uint32_t j = PS1[na + k];
+        const typename C::U u = C::enc(x);
+        const int64_t lo = bound_in<C, false>(S1, na, u);
+        // keys equal to x among the kept ones: usually none
+        int64_t hi = lo;
+        if (lo < na && C::enc(S1[lo]) == u) hi = lo + bound_in<C, true>(S1 + lo, na - lo, u);
+        const int64_t kb = j < (uint64_t)m ? (int64_t)okb[j] : 0;
+        const int64_t pos = k + (kb < lo ? lo : kb > hi ? hi : kb);
+        if (pos >= 0 && pos < n && j < (uint64_t)m) {
+            Ub[pos] = x;
+            PUb[pos] = opay[j];
+        }
+        PS1[na + k] = (uint32_t)pos;
+    }
+}
+
+// First k in [0, m) with B[k] >= p (B ascending), by one wavefront: 64
+// probes per round narrow the range 64-fold.  Result in every lane.
+__device__ __forceinline__ int64_t lower_bound_wave(const uint32_t* B, int64_t m, int64_t p) {
+    const int lane = (int)__lane_id();
+    int64_t lo = 0, hi = m;  // B[lo - 1] < p <= B[hi]
+    while (lo < hi) {
+        const int64_t len = hi - lo;
+        const int64_t step = (len + kWave - 1) / kWave;
+        const int64_t x = lo + (int64_t)lane * step;
+        const bool below = x < hi && (int64_t)B[x] < p;
+        const int cnt = __builtin_popcountll(__builtin_amdgcn_ballot_w64(below));
+        if (cnt == 0) {
+            hi = lo;
+        } else {
+            const int64_t last = lo + (int64_t)(cnt - 1) * step;
+            const int64_t first_not = lo + (int64_t)cnt * step;
+            lo = last + 1;
+            hi = first_not < hi ? first_not : hi;
+        }
+    }
+    return lo;
+}
+
+// Merge slot P + 1: the kept pairs into the places left free, in order:
+// output p (not an outlier's place) takes A[p - (outlier places below p)].
+// Chunks of WG * 16 outputs, grid-stride; a chunk's outlier places as an
+// LDS bitmap with word prefix counts.
+template <class C, int WG>
+__device__ void outlier_fill_pairs(typename C::S* Ub, const typename C::S* S1, uint32_t* PUb, const uint32_t* PS1,
+                                   int64_t n, int64_t m) {
+    constexpr int CHF = WG * 16;
+    constexpr int NWD = CHF / 32;
+    static_assert(NWD <= WG, "one bitmap word per thread");
+    __shared__ unsigned int bm[NWD];
+    __shared__ unsigned int pre[NWD];
+    __shared__ long long s_k[2];
+    const int tid = threadIdx.x;
+    const int64_t na = n - m;
+    const uint32_t* B = PS1 + na;
+    for (int64_t p0 = (int64_t)blockIdx.x * CHF; p0 < n; p0 += (int64_t)gridDim.x * CHF) {
+        const int64_t p1 = (p0 + CHF) < n ? (p0 + CHF) : n;
+        if (tid < NWD) bm[tid] = 0u;
+        if (tid < 2 * kWave) {
+            const int64_t kk = lower_bound_wave(B, m, tid < kWave ? p0 : p1);
+            if (tid == 0) s_k[0] = kk;
+            if (tid == kWave) s_k[1] = kk;
+        }
+        __syncthreads();
+        const int64_t k0 = s_k[0], k1 = s_k[1];
+        for (int64_t k = k0 + tid; k < k1; k += WG) {
+            const int64_t off = (int64_t)B[k] - p0;
+            if (off >= 0 && off < CHF) atomicOr(&bm[off >> 5], 1u << (off & 31));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned int run = 0;
+            for (int w = 0; w < NWD; ++w) {
+                pre[w] = run;
+                run += (unsigned int)__builtin_popcount(bm[w]);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < (int)(p1 - p0); i += WG) {
+            const unsigned int word = bm[i >> 5];
+            const unsigned int bit = 1u << (i & 31);
+            if (word & bit) continue;
+            const int64_t before = k0 + (int64_t)pre[i >> 5] + __builtin_popcount(word & (bit - 1u));
+            const int64_t a = p0 + i - before;
+            if (a >= 0 && a < na) {
+                Ub[p0 + i] = S1[a];
+                PUb[p0 + i] = PS1[a];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ wide few unique
 // The FEW job with 65 to 4096 sampled values (Table 1's few-unique type is
 // 12-limited: 4096 values).  Buckets and job are those above; what changes
@@ -1543,7 +1670,8 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
                                               int64_t n, int M, int64_t T, int k, const Ctl* ctl,
                                               const RunArea* ra, const FewTable* ft,
                                               const unsigned long long* tdesc = nullptr,
-                                              const WideTable* fw = nullptr) {
+                                              const WideTable* fw = nullptr, const uint32_t* opay = nullptr,
+                                              const uint32_t* okb = nullptr) {
     using MC = MergeChunk<C, WG, IT, PAIRS>;
     using S = typename C::S;
     __shared__ typename MC::Smem sm;
@@ -1557,6 +1685,18 @@ __global__ __launch_bounds__(WG) void k_merge(typename C::S* U, typename C::S* S
         if (ctl != nullptr && ft != nullptr && ctl->path == SR_PATH_FEW && k == 0) {
             copy_part(S1, U, PS1, PU, n, (int64_t)blockIdx.x, (int64_t)gridDim.x);
             return;
+        }
+        // OUTLIER of pairs: slot P places the outliers, slot P + 1 the kept pairs
+        if (ctl != nullptr && opay != nullptr && ctl->path == SR_PATH_OUTLIER) {
+            const int P = ctl->job_passes;
+            if (k == P) {
+                outlier_place_pairs<C>(U, S1, PU, PS1, n, (int64_t)ctl->m, opay, okb);
+                return;
+            }
+            if (k == P + 1) {
+                outlier_fill_pairs<C, WG>(U, S1, PU, PS1, n, (int64_t)ctl->m);
+                return;
+            }
         }
     } else {
         if (ctl != nullptr) {
@@ -1591,7 +1731,8 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
                                                       uint32_t* PS1, int64_t n, int M, int64_t T, int k,
                                                       const int64_t* co, const Ctl* ctl, const RunArea* ra,
                                                       const FewTable* ft, const unsigned long long* tdesc = nullptr,
-                                                      int fan4 = 0, const WideTable* fw = nullptr) {
+                                                      int fan4 = 0, const WideTable* fw = nullptr,
+                                                      const uint32_t* opay = nullptr, const uint32_t* okb = nullptr) {
     using MP = MergePersistent<C, WG, IT, PAIRS>;
     using MC = typename MP::MC;
     using S = typename C::S;
@@ -1609,6 +1750,18 @@ __global__ __launch_bounds__(WG) void k_merge_persist(typename C::S* U, typename
         if (ctl != nullptr && ft != nullptr && ctl->path == SR_PATH_FEW && k == 0) {
             copy_part(S1, U, PS1, PU, n, (int64_t)blockIdx.x, (int64_t)gridDim.x);
             return;
+        }
+        // OUTLIER of pairs: slot P places the outliers, slot P + 1 the kept pairs
+        if (ctl != nullptr && opay != nullptr && ctl->path == SR_PATH_OUTLIER) {
+            const int P = ctl->job_passes;
+            if (k == P) {
+                outlier_place_pairs<C>(U, S1, PU, PS1, n, (int64_t)ctl->m, opay, okb);
+                return;
+            }
+            if (k == P + 1) {
+                outlier_fill_pairs<C, WG>(U, S1, PU, PS1, n, (int64_t)ctl->m);
+                return;
+            }
         }
     } else {
         if (ctl != nullptr) {
@@ -1903,7 +2056,7 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
                                                     typename C::S* s1, const unsigned int* flags,
                                                     const unsigned long long* kpref_t, const RunArea* ra,
                                                     uint32_t* pay, uint32_t* spay, const FewTable* ft,
-                                                    const unsigned int* fewm) {
+                                                    const unsigned int* fewm, uint32_t* opay, uint32_t* okb) {
     using S = typename C::S;
     constexpr int CP = kClsTC / kClsWG;
     constexpr int NW = kClsTC / 32;  // mask words per tile
@@ -1949,6 +2102,10 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
     if (tid < NW) spre[tid] = pre;
     __syncthreads();
     const int64_t kpref = (int64_t)kpref_t[t];
+    // pairs: outliers in input order with their index, payload and kept-before
+    // count (keys only: from the end backwards)
+    const bool pj = opay != nullptr;
+    const int64_t mj = pj ? (int64_t)ctl->m : 0;
 #pragma unroll
     for (int r = 0; r < CP; ++r) {
         const int li = r * kClsWG + tid;
@@ -1957,10 +2114,23 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
             const unsigned int word = sw[li >> 5];
             const int bit = li & 31;
             const int kr = spre[li >> 5] + __builtin_popcount(word & ((1u << bit) - 1u));
+            const bool keep = ((word >> bit) & 1u) != 0u;
+            const int64_t jj = (c0 - kpref) + (li - kr);  // outliers before it
             int64_t pos;
-            if ((word >> bit) & 1u) pos = kpref + kr;
-            else pos = n - 1 - ((c0 - kpref) + (li - kr));
-            if (pos >= 0 && pos < n) s1[pos] = x[r];
+            if (keep) pos = kpref + kr;
+            else pos = pj ? n - mj + jj : n - 1 - jj;
+            if (pos >= 0 && pos < n) {
+                s1[pos] = x[r];
+                if (pj) {
+                    if (keep) {
+                        spay[pos] = pay[g];
+                    } else if (jj < mj) {
+                        spay[pos] = (uint32_t)jj;
+                        opay[jj] = pay[g];
+                        okb[jj] = (uint32_t)(kpref + kr);
+                    }
+                }
+            }
         }
     }
 }
@@ -1976,7 +2146,7 @@ __global__ __launch_bounds__(kClsWG) void k_scatter(typename C::S* keys, int64_t
 // cheaper of the two is kept.
 __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
                                 const unsigned long long* tlast, const unsigned long long* tcount,
-                                unsigned long long* kpref_t, int64_t T_sort, double* ocost);
+                                unsigned long long* kpref_t, int64_t T_sort, double* ocost, int pairs, int M);
 
 template <class C>
 __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
@@ -1984,7 +2154,7 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
                                                    unsigned long long* kpref_t, int64_t T_sort,
                                                    const typename C::S* keys, const RunTile* rdesc, RunArea* ra,
                                                    int runs_ok, int64_t merge_ch, int M, FewTable* ft,
-                                                   WideTable* fw, unsigned int* fewm) {
+                                                   WideTable* fw, unsigned int* fewm, int out_pairs) {
     const int path0 = ctl->path;
     if (path0 == SR_PATH_FEW) {
         if (fewm != nullptr) few_plan_pairs(ctl, n, ft, fewm, ntiles);
@@ -1994,7 +2164,8 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
     }
     const bool want_runs = runs_ok && (path0 == SR_PATH_RUNS || (path0 == SR_PATH_OUTLIER && ctl->dual));
     __shared__ double s_ocost;
-    if (path0 == SR_PATH_OUTLIER) verify_outliers(ctl, n, ntiles, tfirst, tlast, tcount, kpref_t, T_sort, &s_ocost);
+    if (path0 == SR_PATH_OUTLIER)
+        verify_outliers(ctl, n, ntiles, tfirst, tlast, tcount, kpref_t, T_sort, &s_ocost, out_pairs, M);
     else if (path0 == SR_PATH_RUNS && threadIdx.x == 0) s_ocost = 1e300;
     __syncthreads();
     // a run plan cannot beat an outlier job of about two passes
@@ -2005,7 +2176,7 @@ __global__ __launch_bounds__(kVerWG) void k_verify(Ctl* ctl, int64_t n, int64_t 
 
 __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsigned long long* tfirst,
                                 const unsigned long long* tlast, const unsigned long long* tcount,
-                                unsigned long long* kpref_t, int64_t T_sort, double* ocost) {
+                                unsigned long long* kpref_t, int64_t T_sort, double* ocost, int pairs, int M) {
     // Rounds of kVerWG x kVerQ consecutive tiles (each thread kVerQ
     // consecutive ones, read from the ver_slot layout so that every load of a
     // wavefront is one coalesced row): the kept prefix
@@ -2098,7 +2269,10 @@ __device__ void verify_outliers(Ctl* ctl, int64_t n, int64_t ntiles, const unsig
         const unsigned long long total = s_base;
         const bool fail = s_bad != 0 || ld_agent(&ctl->bad_join) != 0 || total > (unsigned long long)n;
         const int64_t m = n - (int64_t)total;
-        if (fail || m > n / 2) {
+        // pairs: at most n/4 outliers, and merge slots for the job's passes
+        // and the two placement passes
+        const int jp0 = ceil_log2_dev((m + T_sort - 1) / T_sort);
+        if (fail || m > (pairs ? n / 4 : n / 2) || (pairs && jp0 + 2 > M)) {
             ctl->path = SR_PATH_GENERAL;
             ctl->m = 0;
             ctl->job_passes = 0;
@@ -2925,7 +3099,7 @@ constexpr double kPassFloorUs = 8.0;
 
 int g_force_path = -1;
 bool g_profile = false;
-bool g_outlier_enabled = true;  // allow the OUTLIER path for keys-only sorts
+bool g_outlier_enabled = true;  // allow the OUTLIER path
 bool g_runs_enabled = true;     // allow the RUNS path for keys-only sorts
 bool g_few_enabled = true;      // allow the FEW path
 bool g_near_enabled = true;     // allow the NEAR plan on general sorts
@@ -3390,7 +3564,8 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
         return SR_OK;
     }
     const int64_t nchunks = cdiv(n, CH);
-    const bool outlier_ok = !PAIRS && g_outlier_enabled;
+    // pairs: outlier places and kept-before counts kept in 32 bits
+    const bool outlier_ok = g_outlier_enabled && (!PAIRS || n <= (int64_t)UINT32_MAX);
     // keys-only sorts and pairs with tiles of whole run-scan tiles (the
     // run reversal of pairs is the stable one)
     const bool runs_ok = g_runs_enabled && T >= kClsTC;
@@ -3433,7 +3608,10 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     const size_t tdesc_bytes = near_ok ? round_up((size_t)ntiles * 32, 256) : 0;
     // FEW with more than 64 splitters: its tables
     const size_t wide_bytes = few_ok ? round_up(sizeof(WideTable), 256) : 0;
-    const size_t data_need = co_bytes + kbytes + (PAIRS ? (size_t)n * 4 : 0);
+    // pairs OUTLIER: each outlier's payload and kept-before count (m <= n/4)
+    const size_t ocap = PAIRS && outlier_ok ? (size_t)n / 4 + 1 : 0;
+    const size_t data_need =
+        co_bytes + kbytes + (PAIRS ? round_up((size_t)n * 4, 256) + round_up(ocap * 8, 256) : 0);
     const size_t aux_need = 4 * cls_arr + flag_bytes + rdesc_bytes + rarea_bytes + tdesc_bytes + wide_bytes;
     sr_status s;
     if (capturing && !(noalloc ? noalloc_ready() : workspace_fits(st, data_need, aux_need)))
@@ -3453,6 +3631,9 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
     int64_t* co = reinterpret_cast<int64_t*>(wd);
     S* skeys = reinterpret_cast<S*>(wd + co_bytes);
     uint32_t* spay = PAIRS ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes) : nullptr;
+    uint32_t* opay = ocap ? reinterpret_cast<uint32_t*>(wd + co_bytes + kbytes + round_up((size_t)n * 4, 256))
+                          : nullptr;
+    uint32_t* okb = ocap ? opay + ocap : nullptr;
     const bool merge8 = sizeof(S) == 4 && !PAIRS && TN::MIT == 16 && sh.merge_items == 8;
     const int64_t merge_ch = use_partition ? CH : (merge8 ? (int64_t)TN::MWG * 8 : CH);
     RunTile* rdesc = nullptr;
@@ -3506,13 +3687,14 @@ sr_status sort_impl(void* keys_v, uint32_t* pay, int64_t n, hipStream_t st, bool
             hipLaunchKernelGGL(k_verify<C>, dim3(1), dim3(kVerWG), 0, ls, ctl, n, ncls,
                                (const unsigned long long*)tfirst, (const unsigned long long*)tlast,
                                (const unsigned long long*)tcount, kpref_t, (int64_t)T, (const S*)keys,
-                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab, fw, fewm);
+                               (const RunTile*)rdesc, rarea, runs_ok ? 1 : 0, merge_ch, M, ftab, fw, fewm,
+                               ocap ? 1 : 0);
             SR_LAUNCH_CHECK("verify");
         }
         ProfScope ps(ls, "scatter");
         hipLaunchKernelGGL(k_scatter<C>, dim3((unsigned)ncls), dim3(kClsWG), 0, ls, keys, n, (const Ctl*)ctl, skeys,
                            (const unsigned int*)flags, (const unsigned long long*)kpref_t, (const RunArea*)rarea,
-                           PAIRS ? pay : nullptr, spay, (const FewTable*)ftab, (const unsigned int*)fewm);
+                           PAIRS ? pay : nullptr, spay, (const FewTable*)ftab, (const unsigned int*)fewm, opay, okb);
         SR_LAUNCH_CHECK("scatter");
     }
     {
@@ -3569,7 +3751,7 @@ tile_done:
                 hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M,
                                    (int64_t)T, k, (const int64_t*)co, (const Ctl*)ctl, (const RunArea*)rarea,
                                    (const FewTable*)ftab, (const unsigned long long*)tdesc, fan4 ? 1 : 0,
-                                   (const WideTable*)fw);
+                                   (const WideTable*)fw, (const uint32_t*)opay, (const uint32_t*)okb);
                 SR_LAUNCH_CHECK("merge");
             }
             if (four) {
@@ -3593,7 +3775,8 @@ tile_done:
                     hipLaunchKernelGGL((k_merge<C, TN::MWG, 8, PAIRS>), dim3((unsigned)(cdiv(n, TN::MWG * 8) + extra)),
                                        dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                        (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
-                                       (const unsigned long long*)tdesc, (const WideTable*)fw);
+                                       (const unsigned long long*)tdesc, (const WideTable*)fw,
+                                       (const uint32_t*)opay, (const uint32_t*)okb);
                     done = true;
                 }
             }
@@ -3601,7 +3784,8 @@ tile_done:
                 hipLaunchKernelGGL((k_merge<C, TN::MWG, TN::MIT, PAIRS>), dim3((unsigned)(nchunks + extra)),
                                    dim3(TN::MWG), 0, ls, keys, skeys, pay, spay, n, M, (int64_t)T, k,
                                    (const Ctl*)ctl, (const RunArea*)rarea, (const FewTable*)ftab,
-                                   (const unsigned long long*)tdesc, (const WideTable*)fw);
+                                   (const unsigned long long*)tdesc, (const WideTable*)fw,
+                                   (const uint32_t*)opay, (const uint32_t*)okb);
             SR_LAUNCH_CHECK("merge");
         }
     }
@@ -4088,7 +4272,8 @@ sr_status sr_workspace_bytes(sr_dtype dt, int with_payload, size_t n, size_t nse
     // run plan; segment plan arrays
     const size_t ncls = n / kClsTC + 1;
     size_t b = kHdrBytes + round_up((n / 2048 + 2 + kRunMaxLeaves) * 8, 256);
-    b += round_up(n * (size_t)es, 256) + (with_payload ? round_up(n * 4, 256) : 0);
+    b += round_up(n * (size_t)es, 256) +
+         (with_payload ? round_up(n * 4, 256) + round_up((n / 4 + 1) * 8, 256) : 0);
     b += 4 * round_up(round_up(ncls, (size_t)kVerRound) * 8, 256) + round_up(ncls * (kClsTC / 8), 256);
     b += round_up(ncls * sizeof(RunTile), 256) + round_up(sizeof(RunArea), 256);
     b += round_up((nseg + 1) * 8 * 4, 256);
@@ -4127,10 +4312,11 @@ sr_status sr_last_stats(void* stream, sr_stats* out) {
         case SR_PATH_OUTLIER: {
             const double m = (double)h.m;
             out->outliers = (int64_t)h.m;
-            out->merge_passes = h.job_passes + 1;
             // classify (n read, n written) + outlier sort (tile + P merges on m)
-            // + final merge of kept and outliers (n read, n written)
-            eq = 2.0 + (1.0 + h.job_passes) * m / (double)lc.n;
+            // + final merge of kept and outliers (n read, n written); pairs:
+            // two placement passes, the outliers' (m) and the kept pairs' (n)
+            out->merge_passes = h.job_passes + (lc.pairs ? 2 : 1);
+            eq = 2.0 + (lc.pairs ? 2.0 + h.job_passes : 1.0 + h.job_passes) * m / (double)lc.n;
             break;
         }
         case SR_PATH_FEW: {

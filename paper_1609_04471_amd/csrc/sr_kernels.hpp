@@ -1072,8 +1072,10 @@ __device__ __forceinline__ void near_check(Ctl* ctl, const unsigned long long* t
 // read from the plan in the control block.  GENERAL sorts the user buffer U
 // with ping-pong partner S1 in M merge passes.  OUTLIER sorts the m outliers
 // (stored at S1[n-m, n)) with partner U in P passes, then merge slot P merges
-// the kept keys S1[0, n-m) with the sorted outliers into U.  FEW sorts its m
-// between-bucket keys the same way; its slot P is the fill pass.
+// the kept keys S1[0, n-m) with the sorted outliers into U (pairs: the
+// outliers carry their indices in PS1[n-m, n) with partner PU, and slots P
+// and P + 1 place them and the kept pairs).  FEW sorts its m between-bucket
+// keys the same way; its slot P is the fill pass.
 template <class S>
 struct PassView {
     const S* src;
@@ -1166,14 +1168,17 @@ __device__ __forceinline__ PassView<S> resolve_merge(const Ctl* ctl, S* U, S* S1
         const int64_t m = (int64_t)ctl->m;
         const int P = ctl->job_passes;
         S* X0 = S1 + (n - m);
+        uint32_t* XP0 = PS1 != nullptr ? PS1 + (n - m) : nullptr;  // pairs: the outliers' indices
         if (k < P) {
             const int from = (P - k) & 1;
             v.src = from ? U : X0;
             v.dst = from ? X0 : U;
+            v.psrc = from ? PU : XP0;
+            v.pdst = from ? XP0 : PU;
             v.n = m;
             v.width = T << k;
             v.active = true;
-        } else if (k == P && path == 2) {
+        } else if (k == P && path == 2 && PS1 == nullptr) {  // keys; pairs place in slots P, P + 1
             v.src = S1;
             v.dst = U;
             v.n = n;
@@ -1206,10 +1211,11 @@ __device__ __forceinline__ PassView<S> resolve_tile(const Ctl* ctl, S* U, S* S1,
         S* X0 = S1 + (n - m);
         // passes after the tile sort: M two-way, or M/2 four-way (+1 two-way)
         const bool odd = ((fan4 && path == 3 ? M / 2 + (M & 1) : M) & 1) != 0;
+        uint32_t* XP0 = PS1 != nullptr ? PS1 + (n - m) : nullptr;  // pairs: the outliers' indices
         src = job ? X0 : U;
         dst = job ? ((P & 1) ? U : X0) : (odd ? S1 : U);
-        psrc = job ? nullptr : PU;
-        pdst = job ? nullptr : (odd ? PS1 : PU);
+        psrc = job ? XP0 : PU;
+        pdst = job ? ((P & 1) ? PU : XP0) : (odd ? PS1 : PU);
         len = job ? m : n;
         active = general || job;
     }

@@ -211,6 +211,65 @@ def test_outlier_path_nearly_sorted(gpu, n):
     assert gpu.last_stats()["path"] == "outlier"
 
 
+def _check_pairs(gpu, k, dtype="int32", p=None):
+    if p is None:
+        p = np.arange(k.size, dtype=np.uint32)
+    gk, gp = gpu_sort_pairs(gpu, k, p, dtype)
+    wk, wp = oracle.sort_pairs(k, p)
+    assert np.array_equal(bits(gk), bits(wk)) and np.array_equal(gp, wp), (dtype, k.size)
+    return gpu.last_stats()
+
+
+@pytest.mark.parametrize("n", [8193, 65_536, 300_007, 2_000_000, 5_000_011])
+def test_outlier_path_pairs_stable(gpu, n):
+    """Pairs on the outlier path: equal keys among the kept keys and among the
+    outliers, and between the two, keep their input order (payload = input
+    position, compared with the oracle's stable sort)."""
+    for seed, (frac, ties) in enumerate([(100, 1), (100, 7), (200, 64), (1000, 3)]):
+        a = _near(n, seed + 10, frac, ties)
+        st = _check_pairs(gpu, a)
+        if n >= 65_536:
+            assert st["path"] == "outlier", (frac, ties, st)
+            assert 0 < st["outliers"] <= n // 4, st
+    b = inputs.nearly_sorted_int32(n, seed=6)
+    assert _check_pairs(gpu, b)["path"] in (("outlier",) if n >= 65_536 else ("outlier", "general"))
+
+
+def test_outlier_path_pairs_other_dtypes_and_payloads(gpu):
+    n = 700_001
+    rng = np.random.default_rng(21)
+    f = np.sort(inputs.normal_float32(n, seed=9, specials=False))
+    f[::1000] = np.float32(0.0)          # ties inside the kept keys and with outliers
+    idx = rng.choice(n, size=2 * (n // 150), replace=False)
+    f[idx[0::2]], f[idx[1::2]] = f[idx[1::2]].copy(), f[idx[0::2]].copy()
+    pay = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    assert _check_pairs(gpu, f, "float32", pay)["path"] == "outlier"
+    u = (np.arange(n, dtype=np.uint64) // np.uint64(5)) * np.uint64(2**35)
+    u[idx[0::2]], u[idx[1::2]] = u[idx[1::2]].copy(), u[idx[0::2]].copy()
+    assert _check_pairs(gpu, u, "uint64")["path"] == "outlier"
+
+
+def test_outlier_path_pairs_limits(gpu):
+    """More than n/4 outliers: the pairs plan falls back to GENERAL before
+    writing anything; forcing OUTLIER on random pairs falls back too; the
+    switch turns the path off."""
+    n = 1_000_003
+    a = _near(n, 3, frac=6, ties=1)       # ~1/3 of the keys displaced
+    assert _check_pairs(gpu, a)["path"] != "outlier"
+    gpu.set_option("force_path", 2)
+    try:
+        r = inputs.random_int32(300_001, seed=4)
+        assert _check_pairs(gpu, r)["path"] == "general"
+        assert _check_pairs(gpu, _near(400_000, 5))["path"] == "outlier"
+    finally:
+        gpu.set_option("force_path", -1)
+    gpu.set_option("outlier_path", 0)
+    try:
+        assert _check_pairs(gpu, _near(400_000, 6))["path"] != "outlier"
+    finally:
+        gpu.set_option("outlier_path", 1)
+
+
 def test_outlier_path_falls_back(gpu):
     n = 1_000_003
     rot = np.concatenate([np.arange(n // 2, n), np.arange(0, n // 2)]).astype(np.int32)
