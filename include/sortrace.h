@@ -58,7 +58,9 @@ typedef enum {
     SR_PATH_TRIVIAL = -1,  /* n <= 1, or small enough for one tile: no probe */
     SR_PATH_SORTED = 0,    /* already nondecreasing: nothing written */
     SR_PATH_REVERSED = 1,  /* nonincreasing: reversed in place (stable for pairs) */
-    SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back */
+    SR_PATH_OUTLIER = 2,   /* nearly sorted: outliers split off, sorted, merged back
+                              (pairs: at most n/4 outliers, n < 2^32; an outlier
+                              and a kept key with equal keys keep input order) */
     SR_PATH_GENERAL = 3,   /* tile sort + merge passes */
     SR_PATH_RUNS = 4,      /* natural runs (keys and pairs; for pairs the reversal
                               keeps equal keys in input order):
@@ -326,7 +328,7 @@ const char *sr_last_error_message(void);
                  SR_PATH_NEAR, so the full merge tree runs).
  *   "profile"     1 = record a HIP event pair around every kernel the sort
  *                 path launches (on the caller's stream); 0 = off (default).
- *   "outlier_path" 1 = keys-only sorts may take SR_PATH_OUTLIER (default);
+ *   "outlier_path" 1 = sorts may take SR_PATH_OUTLIER (default);
  *                 0 = never (nearly sorted input then takes SR_PATH_GENERAL).
  *   "few_path"    1 = sorts may take SR_PATH_FEW (default); 0 = never.
  *                 A forced SR_PATH_FEW still falls back to SR_PATH_GENERAL when
