@@ -299,6 +299,44 @@ __device__ __forceinline__ int64_t corank_thread(const typename C::S* A, int64_t
     return lo;
 }
 
+// corank_thread with a first guess, for the partition launch: when A and B
+// are alike (the general plan's runs of random keys), the co-rank of d lies
+// within a few sqrt(d) of d * la / (la + lb).  A window of +-(4 sqrt(d) + 64)
+// around that guess is checked with two probes issued together (it holds the
+// co-rank iff A[lo'-1] <= B[d-lo'] and A[hi'] > B[d-1-hi'], or it touches the
+// range's ends) and then searched; when the check fails the whole range is.
+// Ranges of at most 4096 are searched directly.
+template <class C>
+__device__ __forceinline__ int64_t corank_guess(const typename C::S* A, int64_t la, const typename C::S* B,
+                                                int64_t lb, int64_t d) {
+    int64_t lo = d > lb ? d - lb : 0;
+    int64_t hi = d < la ? d : la;
+    if (hi - lo > 4096) {
+        const int64_t g = (int64_t)((double)d * (double)la / (double)(la + lb));
+        const int64_t w = 4 * (int64_t)sqrt((double)d) + 64;
+        const int64_t glo = g - w > lo ? g - w : lo;
+        const int64_t ghi = g + w < hi ? g + w : hi;
+        // the two probes' keys, loaded before either is compared; a range
+        // this wide has la, lb >= 1, so index 0 stands in for an unused probe
+        const typename C::U a0 = C::enc(A[glo > lo ? glo - 1 : 0]), b0 = C::enc(B[glo > lo ? d - glo : 0]);
+        const typename C::U a1 = C::enc(A[ghi < hi ? ghi : 0]), b1 = C::enc(B[ghi < hi ? d - 1 - ghi : 0]);
+        const bool ok_lo = glo == lo || a0 <= b0;
+        const bool ok_hi = ghi == hi || !(a1 <= b1);
+        if (glo <= ghi && ok_lo && ok_hi) {
+            lo = glo;
+            hi = ghi;
+        }
+    }
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (C::enc(A[mid]) <= C::enc(B[d - 1 - mid]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Same search in global memory by one whole wavefront: each round the 64
 // lanes test 64 evenly spaced candidates, so the range shrinks 64-fold per
 // round.  Keys are decoded with codec C on load.  Returns the co-rank in all

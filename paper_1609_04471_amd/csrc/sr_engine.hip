@@ -1661,7 +1661,7 @@ __global__ __launch_bounds__(256) void k_partition(typename C::S* U, typename C:
         const int64_t rest = v.n - gs - la;
         lb = rest < v.width ? rest : v.width;
     }
-    co[c] = corank_thread<C>(v.src + gs, la, v.src + gs + la, lb, out0 - gs);
+    co[c] = corank_guess<C>(v.src + gs, la, v.src + gs + la, lb, out0 - gs);
 }
 
 // Merge slot k, one chunk per workgroup, co-ranks searched in the workgroup.
