@@ -2343,25 +2343,28 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
         b0 = std::max<int64_t>(0, std::min<int64_t>(b0, npairs - kProbeSample));
         const int64_t s1 = std::min<int64_t>(b0 + kProbeSample, npairs);
         for (int64_t i = b0 + tid; i < s1; i += kProbeWG) {
+            // every key the tests below may look at, loaded together (indexes
+            // clamped into the array; a test uses a key only where its index
+            // was in range), so that the sample costs one round trip
+            const int64_t last = n - 1;
+            const U w = C::enc(keys[i > 0 ? i - 1 : 0]);
             const U x = C::enc(keys[i]), y = C::enc(keys[i + 1]);
+            const U z = C::enc(keys[i + 2 < last ? i + 2 : last]);
+            const U u = C::enc(keys[i + 3 < last ? i + 3 : last]);
+            const U far = C::enc(keys[i + 1 + kDropDepth < last ? i + 1 + kDropDepth : last]);
             seen_desc |= x > y;
             seen_asc |= x < y;
             sd += x > y ? 1 : 0;
             sp += x == y ? (1ull << kSampleField) + 1 : 1;
             if (i + 1 < npairs) {
-                const U z = C::enc(keys[i + 2]);
                 if ((x > y && y < z) || (x < y && y > z)) sd += 1ull << kSampleField;
                 if (x > y && y < z && x >= z) {
                     sp += 1ull << (2 * kSampleField);
                 } else if (x > y && y == z && i + 2 < npairs) {  // a valley on a plateau of two
-                    const U u = C::enc(keys[i + 3]);
                     if (y < u && x >= u) sp += 1ull << (2 * kSampleField);
                 }
-                if (x > y && y <= z && x > z && i > 0 && i + 1 + kDropDepth < n) {
-                    const U w = C::enc(keys[i - 1]);
-                    const U far = C::enc(keys[i + 1 + kDropDepth]);
+                if (x > y && y <= z && x > z && i > 0 && i + 1 + kDropDepth < n)
                     sdd += (w <= x && w > y && far < x) ? 1 : 0;
-                }
             }
         }
     }
@@ -2370,7 +2373,8 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
     const int any_desc = __syncthreads_or((int)seen_desc);
     const int any_asc = __syncthreads_or((int)seen_asc);
     const bool sample_mixed = any_desc != 0 && any_asc != 0;
-    if (sample_mixed && tid == 0 && ld_agent(&ctl->mixed) == 0u) atomicOr(&ctl->mixed, 1u);
+    // (the atomic's result is not waited for: raising the flag costs no round trip)
+    if (sample_mixed && tid == 0) atomicOr(&ctl->mixed, 1u);
     unsigned long long d = 0, a = 0;
     const bool vec_ok = aligned16(keys);
     for (int64_t t = blockIdx.x; !sample_mixed && t < ntiles; t += gridDim.x) {
@@ -2425,7 +2429,7 @@ __global__ __launch_bounds__(kProbeWG) void k_probe(const typename C::S* keys, i
             d += sdn;
             a += san;
             if (d && a) {
-                if (ld_agent(&ctl->mixed) == 0u) atomicOr(&ctl->mixed, 1u);
+                atomicOr(&ctl->mixed, 1u);
                 skip = 1;
             }
         }
