@@ -378,8 +378,14 @@ struct MergeChunk {
     static constexpr int ITEMS = IT;
     static constexpr int VN = 16 / sizeof(S);
     static constexpr int PADDED = CH + CH / 16;
+    // keys only: GAP slots of the largest code after each staged run (A at
+    // [0, na), B at [na + GAP, cnt + GAP)), so that the serial merge reads
+    // past a run's end without a bounds test
+    static constexpr int GAP = PAIRS ? 0 : IT;
     static_assert(WG >= 2 * kWave, "two wavefronts search the window bounds");
     static_assert(IT % VN == 0, "whole vectors per thread");
+    static_assert(PADDED >= CH + 2 * GAP + 1, "both runs, their stops and one read past them fit the buffer");
+    static_assert(WG >= 2 * GAP, "one thread per stop slot");
 
     struct Buf {
         U k[PADDED];
@@ -510,10 +516,11 @@ struct MergeChunk {
         }
     }
 
-    // The loaded blocks into LDS: A at [0, na), B at [na, cnt), keys encoded.
+    // The loaded blocks into LDS: A at [0, na), B at [na + gap, cnt + gap),
+    // keys encoded.
     template <class T, int TN, class F>
     static __device__ __forceinline__ void stage_blocks(const V16<T> (&x)[(TN == 0 ? 1 : TN)], int na, int nb,
-                                                        int offA, int offB, int nbA, int nbB, F&& put) {
+                                                        int offA, int offB, int nbA, int nbB, int gap, F&& put) {
         constexpr int E = 16 / (int)sizeof(T);
 #pragma unroll
         for (int r = 0; r < TN; ++r) {
@@ -522,7 +529,7 @@ struct MergeChunk {
                 const bool inA = blk < nbA;
                 const int e0 = inA ? blk * E - offA : (blk - nbA) * E - offB;  // part-relative index of x.v[0]
                 const int lim = inA ? na : nb;
-                const int to = inA ? 0 : na;
+                const int to = inA ? 0 : na + gap;
                 if (e0 >= 0 && e0 + E <= lim) {
 #pragma unroll
                     for (int j = 0; j < E; ++j) put(to + e0 + j, x[r].v[j]);
@@ -537,11 +544,15 @@ struct MergeChunk {
 
     static __device__ __forceinline__ void stage(Buf& b, const Win& w) {
         const int nb = w.cnt - w.na;
-        stage_blocks<S, RV>(w.x, w.na, nb, w.offA, w.offB, w.nbA, w.nbB,
+        stage_blocks<S, RV>(w.x, w.na, nb, w.offA, w.offB, w.nbA, w.nbB, GAP,
                             [&](int e, S v) { b.k[e] = C::enc(v); });
         if constexpr (PAIRS) {
             stage_blocks<uint32_t, RVP>(reinterpret_cast<const V16<uint32_t>(&)[RVP]>(w.px), w.na, nb, w.poffA,
-                                        w.poffB, w.pnbA, w.pnbB, [&](int e, uint32_t v) { b.pay[e] = v; });
+                                        w.poffB, w.pnbA, w.pnbB, 0, [&](int e, uint32_t v) { b.pay[e] = v; });
+        } else {
+            // the stops after A and after B
+            const int t = threadIdx.x;
+            if (t < 2 * GAP) b.k[t < GAP ? w.na + t : w.cnt + t] = ~(U)0;
         }
     }
 
@@ -550,35 +561,38 @@ struct MergeChunk {
         const int t0 = threadIdx.x * IT;
         if (t0 >= cnt) return;
         const int nb = cnt - na;
+        const int b0 = na + GAP;  // first staged B slot
         int i;
         {
-            // co-rank of t0 between the staged A = [0, na) and B = [na, cnt)
+            // co-rank of t0 between the staged A = [0, na) and B = [b0, b0 + nb)
             int lo = t0 > nb ? t0 - nb : 0;
             int hi = t0 < na ? t0 : na;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (b.k[mid] <= b.k[na + t0 - 1 - mid]) lo = mid + 1;
+                if (b.k[mid] <= b.k[b0 + t0 - 1 - mid]) lo = mid + 1;
                 else hi = mid;
             }
             i = lo;
         }
         int j = t0 - i;
         if constexpr (!PAIRS) {
-            // Keys only: an exhausted run reads as the largest code.  Taking
-            // that stand-in instead of an equal key of the other run writes
+            // Keys only: an exhausted run reads its stops, the largest code.
+            // Taking a stop instead of an equal key of the other run writes
             // the same bits, and every key still to come is then that value
-            // too (both runs are sorted), so the output is exact.
-            constexpr U kMax = ~(U)0;
-            int pa = i, pb = na + j;
-            U a = pa < na ? b.k[pa] : kMax, bb = pb < cnt ? b.k[pb] : kMax;
+            // too (both runs are sorted), so the output is exact.  A run's
+            // index passes its end only while both heads hold the largest
+            // code, one slot per output: with IT stops only the read after
+            // the last output (never used) can land past them, at most at
+            // cnt + 2 GAP, inside the buffer.
+            int pa = i, pb = b0 + j;
+            U a = b.k[pa], bb = b.k[pb];
 #pragma unroll
             for (int r = 0; r < IT; ++r) {
                 const bool ta = a <= bb;
                 v[r] = ta ? a : bb;
                 pa += ta ? 1 : 0;
                 pb += ta ? 0 : 1;
-                const int nx = ta ? pa : pb;        // <= cnt < PADDED: inside the buffer
-                const U kn = nx < (ta ? na : cnt) ? b.k[nx] : kMax;
+                const U kn = b.k[ta ? pa : pb];
                 a = ta ? kn : a;
                 bb = ta ? bb : kn;
             }
