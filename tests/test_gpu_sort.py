@@ -511,3 +511,33 @@ def test_random_sizes_sweep(gpu):
         else:
             got = gpu_sort_keys(gpu, a, dt)
             assert np.array_equal(bits(got), bits(oracle.sort_keys(a))), (case, n, kind, dt)
+
+
+@pytest.mark.parametrize("path", [-1, 3])
+@pytest.mark.parametrize("n", [40_000, 300_001, 2_000_000, 9_000_001])
+def test_largest_code_keys_through_the_merges(gpu, n, path):
+    """Keys equal to the largest code of their type (INT32_MAX, 2^64 - 1, and
+    the float32 NaN with every payload bit set, last in totalOrder) -- the
+    value a keys-only merge stages after each run -- mixed with random keys,
+    in runs of them and alone, on the device's own path (-1) and forced
+    through the general merge passes (3); every size up to the separate
+    partition launch's shape.  Exact against the oracle."""
+    rng = np.random.default_rng(n + path)
+    biggest = {"int32": np.array([2**31 - 1], np.int32),
+               "uint64": np.array([2**64 - 1], np.uint64),
+               "float32": np.array([0x7FFFFFFF], np.uint32).view(np.float32)}
+    for dtype, big in biggest.items():
+        if dtype == "uint64":
+            a = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64)
+        elif dtype == "int32":
+            a = rng.integers(-2**31, 2**31 - 1, size=n, dtype=np.int32)
+        else:
+            a = inputs.normal_float32(n, seed=n + 11)
+        a[rng.random(n) < 0.3] = big[0]
+        a[n // 3:n // 3 + 5000] = big[0]
+        gpu.set_option("force_path", path)
+        try:
+            got = gpu_sort_keys(gpu, a, dtype)
+        finally:
+            gpu.set_option("force_path", -1)
+        assert np.array_equal(bits(got), bits(oracle.sort_keys(a))), (dtype, n, path)
