@@ -541,3 +541,32 @@ def test_largest_code_keys_through_the_merges(gpu, n, path):
         finally:
             gpu.set_option("force_path", -1)
         assert np.array_equal(bits(got), bits(oracle.sort_keys(a))), (dtype, n, path)
+
+
+@pytest.mark.parametrize("n", [9_000_001, 20_000_003])
+def test_job_passes_on_the_partition_shape(gpu, n):
+    """Sizes that take the separate partition launch (int32 keys from 2^23):
+    the merge passes of an outlier job and of a few-unique job with keys
+    between the sampled values, each behind its own partition launch on the
+    job's short runs; keys and pairs, exact against the oracle."""
+    a = _near(n, n)
+    got = gpu_sort_keys(gpu, a, "int32")
+    st = gpu.last_stats()
+    assert st["path"] == "outlier" and st["merge_passes"] >= 3, st
+    assert np.array_equal(got, oracle.sort_keys(a))
+    p = np.arange(n, dtype=np.uint32)
+    gk, gp = gpu_sort_pairs(gpu, a, p, "int32")
+    st = gpu.last_stats()
+    assert st["path"] == "outlier", st
+    wk, wp = oracle.sort_pairs(a, p)
+    assert np.array_equal(gk, wk) and np.array_equal(gp, wp)
+    rng = np.random.default_rng(n)
+    vals = rng.integers(-2**31, 2**31, size=20, dtype=np.int64)
+    b = vals[rng.integers(0, 20, size=n)]
+    other = rng.random(n) < 0.03
+    b[other] = rng.integers(-2**31, 2**31, size=int(other.sum()), dtype=np.int64)
+    b = b.astype(np.int32)
+    got = gpu_sort_keys(gpu, b, "int32")
+    st = gpu.last_stats()
+    assert st["path"] == "few" and st["outliers"] > 0 and st["merge_passes"] >= 3, st
+    assert np.array_equal(got, oracle.sort_keys(b))
