@@ -952,10 +952,23 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
     for (int i = tid; i < ns; i += kClsWG) sp[i] = (U)ft->split[i];
     for (int b = tid; b < nb; b += kClsWG) hist[b] = 0;
     typename C::S x[R];
+    // a whole tile as 16-byte vectors: the order of a tile's keys matters
+    // neither to its counts nor to its between keys (they are sorted later)
+    constexpr int VN = 16 / (int)sizeof(typename C::S);
+    const bool vec = c1 - c0 == kClsTC && aligned16(keys + c0);
+    if (vec) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t q = c0 + r * kClsWG + tid;
-        if (q < c1) x[r] = keys[q];
+        for (int u = 0; u < R / VN; ++u) {
+            const V16<typename C::S> y = reinterpret_cast<const V16<typename C::S>*>(keys + c0)[u * kClsWG + tid];
+#pragma unroll
+            for (int j = 0; j < VN; ++j) x[u * VN + j] = y.v[j];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t q = c0 + r * kClsWG + tid;
+            if (q < c1) x[r] = keys[q];
+        }
     }
     __syncthreads();
     unsigned long long bm[R];
@@ -963,7 +976,7 @@ __device__ void few_count(const typename C::S* keys, int64_t n, int64_t c0, int6
     for (int r = 0; r < R; ++r) {
         const int64_t q = c0 + r * kClsWG + tid;
         bool between = false;
-        if (q < c1) {
+        if (vec || q < c1) {
             const int b = few_bucket<U>(sp, ns, C::enc(x[r]));
             atomicAdd(&hist[b], 1u);
             between = (b & 1) == 0;
