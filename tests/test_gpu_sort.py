@@ -122,6 +122,23 @@ def test_unaligned_pointers(gpu):
     assert np.array_equal(got[1:], oracle.sort_keys(a[1:]))
 
 
+@pytest.mark.parametrize("n", [70_001, 1_000_003])
+def test_unaligned_pointers_every_path(gpu, n):
+    # every input type (and a 64-value few-unique input) at a base 4-byte
+    # but not 16-byte aligned: the vector loads of the probe, the few-unique
+    # count and the tile sort fall back to element loads
+    kinds = {k: inputs.int32_of_type(k, n + 1, 40 + i) for i, k in enumerate(inputs.TYPES)}
+    kinds["few64"] = inputs.few_unique_int32(n + 1, seed=3, distinct=64)
+    for kind, a in kinds.items():
+        for off in (1, 2, 3):
+            base = to_dev(a)
+            view = base[off:]
+            gpu.sort_keys(view, dtype="int32")
+            got = base.cpu().numpy()
+            assert np.array_equal(got[:off], a[:off]), (kind, off)
+            assert np.array_equal(got[off:], oracle.sort_keys(a[off:])), (kind, off, gpu.last_stats()["path"])
+
+
 def test_paths_chosen(gpu):
     n = 1_000_000
     cases = {"sorted": (np.arange(n, dtype=np.int32), "sorted"),
